@@ -1,0 +1,174 @@
+/*
+ * mpk.h -- C-ABI of the MI355X (gfx950) library for ILU(0)-preconditioned
+ * multiple-precision Krylov solvers (Kouya, "Assessing the Performance of
+ * Mixed-Precision ILU(0)-Preconditioned Multiple-Precision Real and Complex
+ * Krylov Subspace Methods", arXiv 2504.14498).
+ *
+ * Problem (Section 3, the linear system equation): A x = b with A an n x n
+ * sparse non-singular matrix, real or complex, stored in CRS with binary64
+ * entries (the paper's matrices are binary64; Section 3, last paragraph),
+ * and x, b in a multi-component precision.  x0 is taken from x on entry.
+ *
+ * Conventions shared by every call:
+ *  - All array pointers are DEVICE pointers (memory of the current HIP
+ *    device) unless stated otherwise.  The caller owns every buffer; the
+ *    library never allocates or frees device memory.  Calls that need
+ *    scratch space take a caller-provided workspace sized by the matching
+ *    *_workspace_bytes query, aligned to 256 bytes.
+ *  - Precision: mpk_prec = number of binary64 limbs K (1 = binary64 "D",
+ *    2 = double-double "DD", 3 = triple-double "TD", 4 = quad-double "QD";
+ *    Section 2's multi-component types).  A vector of n elements is an array
+ *    of n * C * K doubles, element-major: element i holds the K limbs of the
+ *    real part (leading limb first), then (complex, C = 2) the K limbs of the
+ *    imaginary part.
+ *  - CSR: row_ptr int32[n+1], col_idx int32[nnz] strictly ascending within
+ *    each row, every diagonal entry stored; val: nnz doubles (real) or
+ *    2*nnz doubles ((re, im) interleaved, complex).  nnz < 2^31.
+ *  - stream: a hipStream_t (NULL = the default stream).  Kernels are
+ *    enqueued on it; calls documented as synchronous wait for it.
+ *  - Return value: MPK_OK or a status code below.  Invalid arguments are
+ *    rejected before any device work, leaving outputs untouched.  No call
+ *    aborts or throws.
+ */
+#ifndef MPK_H
+#define MPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { MPK_D = 1, MPK_DD = 2, MPK_TD = 3, MPK_QD = 4 } mpk_prec;
+
+/* The four product-type methods of Section 3 (Algorithm 3 is BiCG). */
+typedef enum { MPK_BICG = 0, MPK_CGS = 1, MPK_BICGSTAB = 2, MPK_GPBICG = 3 } mpk_method;
+
+enum {
+  MPK_OK = 0,
+  MPK_NOT_CONVERGED = 1,  /* max_iter reached; x holds the last iterate      */
+  MPK_BREAKDOWN = 2,      /* a method scalar became exactly zero; x = last  */
+  MPK_EINVAL = -1,        /* bad argument (null pointer, size, precision)    */
+  MPK_EDEVICE = -2,       /* a HIP runtime call failed                       */
+  MPK_EWORKSPACE = -3,    /* workspace missing, too small or misaligned      */
+  MPK_EZERO_PIVOT = -4,   /* ILU(0) met u_kk = 0 (bad_row = k)               */
+  MPK_ENO_DIAG = -5,      /* a diagonal entry is not stored (bad_row = i)    */
+  MPK_EUNSUPPORTED = -6,  /* valid but unsupported combination              */
+  MPK_ENONFINITE = -7,    /* a matrix entry is Inf or NaN (bad_row = i)      */
+  MPK_EPATTERN = -8,      /* columns not strictly ascending or out of range  */
+  MPK_EWATCHDOG = -9      /* a device dependency wait exceeded its bound     */
+};
+
+/* CSR matrix, binary64 values; all pointers device, borrowed. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+} mpk_csr;
+
+/* Solve / factor report (host struct, filled by the library). */
+typedef struct {
+  int64_t iters;            /* passes of the main loop run                    */
+  int64_t bad_row;          /* row of a zero pivot / missing diagonal, else -1 */
+  int32_t status;           /* same as the return value                        */
+  double relres_recursive;  /* ||r_k|| / ||r_0||, recursive residual           */
+  double relres_true;       /* ||b - A x|| / ||b||, checked in the working
+                               precision; -1 if never evaluated                 */
+  double setup_ms;          /* validation, analysis and ILU(0) factorisation   */
+  double solve_ms;          /* iterations and true-residual checks             */
+  double *res_history;      /* optional DEVICE buffer: leading limb of
+                               ||r_k||^2 for k = 1..res_history_len            */
+  int64_t res_history_len;
+} mpk_info;
+
+typedef struct mpk_ilu0 mpk_ilu0; /* opaque, host-side handle */
+
+const char *mpk_status_str(int status);
+int mpk_version(void);
+
+/* ------------------------------------------------------------------ SpMV
+ * y = A x, or y = A^T x (real, trans = 1), or y = A^H x (complex,
+ * conj_trans = 1): the CRS SpMV with binary64 A and a K-limb vector (the
+ * mixed-precision "_d" product of Section 4).  Row i accumulates its
+ * products in ascending column order in the working precision, starting
+ * from the first product; the transposed product uses the explicit
+ * (conjugate) transpose, whose rows list the entries in ascending original
+ * row.  The transposed form needs ws of mpk_spmv_workspace_bytes(A, C, 1)
+ * bytes and synchronizes the stream (it copies the pattern to the host to
+ * build the transpose); the plain form needs no workspace (ws may be NULL)
+ * and is asynchronous.  x and y must not overlap. */
+size_t mpk_spmv_workspace_bytes(const mpk_csr *A, int is_complex, int trans);
+int mpk_dcsr_spmv(mpk_prec xp, const mpk_csr *A, int trans, const double *x, double *y,
+                  void *ws, size_t ws_bytes, void *stream);
+int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x, double *y,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- ILU(0)
+ * ILU(0) factorisation (Algorithm 1) on the stored pattern of A, in factor
+ * precision fp = MPK_D (binary64: the "_d_ILU(0)" factor of Section 4) or
+ * MPK_DD (A promoted exactly to double-word).  "A_ij != 0" is read
+ * structurally.  Rows are eliminated in IKJ order, level by level; each
+ * entry receives the updates of Algorithm 1 in ascending k, so the factor
+ * is identical to the KIJ loop's.  Zero pivots are reported
+ * (MPK_EZERO_PIVOT, bad_row = k), never skipped.  ws (caller-owned, kept
+ * alive until mpk_ilu0_destroy) receives the factor and the level
+ * schedules; *M receives a host handle pointing into it.  flags:
+ * MPK_ILU0_ADJOINT also prepares the M^H solve (needed by
+ * conj_trans = 1 and by BiCG).  Synchronous; info may be NULL. */
+#define MPK_ILU0_ADJOINT 1
+size_t mpk_ilu0_workspace_bytes(const mpk_csr *A, mpk_prec fp, int is_complex, int flags);
+int mpk_dilu0_factor(mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     mpk_ilu0 **M, mpk_info *info, void *stream);
+int mpk_zilu0_factor(mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     mpk_ilu0 **M, mpk_info *info, void *stream);
+
+/* z = M^{-1} r with M = L U (Algorithm 2: unit-lower forward substitution,
+ * then backward substitution with a division by u_ii), or z = M^{-H} r
+ * (conj_trans = 1: forward with U^H dividing by conj(u_ii), then backward
+ * with the unit L^H; Algorithm 3's M^H solve).  Sums run in ascending
+ * column order, each term subtracted in turn.  Vector precision vp >= the
+ * factor precision.  Asynchronous on stream; r and z must not overlap and
+ * must not be in use by another apply of the same handle. */
+int mpk_dilu0_apply(const mpk_ilu0 *M, mpk_prec vp, int conj_trans, const double *r, double *z,
+                    void *stream);
+int mpk_zilu0_apply(const mpk_ilu0 *M, mpk_prec vp, int conj_trans, const double *r, double *z,
+                    void *stream);
+/* Frees the host handle only; the workspace stays the caller's. */
+void mpk_ilu0_destroy(mpk_ilu0 *M);
+
+/* --------------------------------------------------------------- solvers
+ * Solve A x = b with a preconditioned product-type method (Section 3):
+ * BiCG exactly as Algorithm 3; CGS, BiCGSTAB and GPBiCG in right-
+ * preconditioned form (unpreconditioned residual, two M-solves per pass).
+ * vp: vector precision (MPK_D..MPK_QD).  fp: 0 = no preconditioner,
+ * MPK_D or MPK_DD = ILU(0) factor precision.  Stopping rule of Algorithm 3,
+ * ||r|| < tol_rel ||r_0|| + tol_abs, on the recursive residual; when it
+ * passes, the true residual ||b - A x|| is evaluated in the working
+ * precision and must pass the same test, otherwise the recursion goes on.
+ * max_iter bounds the passes.  x: in x0, out the solution (or last
+ * iterate).  Synchronous.  info may be NULL. */
+size_t mpk_krylov_workspace_bytes(mpk_method m, mpk_prec vp, mpk_prec fp, const mpk_csr *A,
+                                  int is_complex);
+int mpk_dkrylov_solve(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel, double tol_abs,
+                      int64_t max_iter, const mpk_csr *A, const double *b, double *x, void *ws,
+                      size_t ws_bytes, mpk_info *info, void *stream);
+int mpk_zkrylov_solve(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel, double tol_abs,
+                      int64_t max_iter, const mpk_csr *A, const double *b, double *x, void *ws,
+                      size_t ws_bytes, mpk_info *info, void *stream);
+
+/* --------------------------------------------------------- inner product
+ * out = <a, b> = sum_i conj(a_i) b_i in the working precision (the inner
+ * products of Algorithm 3), reduced by a fixed tree (deterministic for a
+ * given n).  out: DEVICE pointer to C*K doubles.  ws: at least
+ * mpk_dot_workspace_bytes(n, C, K) bytes.  Asynchronous. */
+size_t mpk_dot_workspace_bytes(int64_t n, int is_complex, mpk_prec p);
+int mpk_dot(mpk_prec p, int is_complex, int64_t n, const double *a, const double *b,
+            double *out, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPK_H */

@@ -1,0 +1,160 @@
+// internal.hpp -- shared host/device definitions of the mpk library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mpk.h"
+#include "mp.hpp"
+
+namespace mpk {
+
+constexpr int BLOCK = 256;          // threads per workgroup for row/element kernels
+constexpr int WAVE = 64;            // CDNA wavefront
+constexpr int MAX_PARTIAL_BLOCKS = 8192;
+constexpr int MAXE = 8;             // max doubles per element (C * K)
+
+// Bit pattern marking "not yet computed" in the outputs of the sync-free
+// triangular solves: a NaN payload that arithmetic never produces (stored
+// results are canonicalised first).
+constexpr uint64_t SENTINEL = 0x7FF4C0DE5E1A7100ull;
+
+// Device-side status of a running solve, in workspace memory.  Every
+// kernel of an iteration reads `done` first and returns if it is set, so
+// work enqueued past convergence or breakdown is a no-op.
+enum : int32_t { ST_RUNNING = 0, ST_CHECK_HALF = 1, ST_CHECK_FULL = 2 };
+
+struct KState {
+  double s[16][MAXE];        // method scalars (K-limb, complex layout re[K] im[K])
+  double nr0sq;              // leading limb of ||r_0||^2
+  double nbsq;               // leading limb of ||b||^2
+  double eps_r, eps_a;
+  double last_nr2;           // leading limb of the last recursive ||r||^2
+  double true_nr2;           // leading limb of the last true ||b - A x||^2
+  int64_t iter;              // passes started
+  int64_t max_iter;
+  int64_t hist_len;
+  double *hist;
+  int32_t done;              // 0 running; 1 finished (see status)
+  int32_t status;            // MPK_OK / MPK_NOT_CONVERGED / MPK_BREAKDOWN
+  int32_t phase;             // ST_RUNNING / ST_CHECK_HALF / ST_CHECK_FULL
+  int32_t x_in_tmp;          // solution left in the temporary vector
+  int32_t first;             // 1 during the first pass
+  int32_t pad[3];
+};
+
+// Scalar slots in KState::s.
+enum {
+  S_RHO = 0, S_RHO_OLD, S_ALPHA, S_BETA, S_OMEGA, S_ZETA, S_ETA, S_SIGMA,
+  S_D0, S_D1, S_D2, S_D3, S_D4, S_D5, S_D6, S_D7
+};
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures, so the same layout code sizes and carves the workspace.
+struct Bump {
+  char *base;
+  size_t off;
+  explicit Bump(void *b) : base(static_cast<char *>(b)), off(0) {}
+  template <class T> T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+// A dependency-ordered schedule for one triangular sweep: rows grouped by
+// level; `seg` splits each level into runs of at most WAVE rows (the work
+// unit of one wavefront, free of internal dependencies).
+struct Plan {
+  int64_t n = 0, nnz = 0;      // rows, dependency entries
+  int32_t nlev = 0, nseg = 0;
+  int32_t *order = nullptr;    // [n] row at each position
+  int32_t *ptr = nullptr;      // [n+1] entry range of each position
+  int32_t *col = nullptr;      // [nnz] dependency column
+  int32_t *src = nullptr;      // [nnz] index of the value in A's pattern
+  int32_t *dsrc = nullptr;     // [n] diagonal position (division plans)
+  int32_t *seg = nullptr;      // [nseg+1] first position of each segment
+  double *val = nullptr;       // [nnz * C * KF] gathered factor values
+  double *dval = nullptr;      // [n * C * KF] gathered pivots
+  int32_t *sync = nullptr;     // [0] ticket, [1] watchdog abort
+  std::vector<int32_t> h_levptr;   // level boundaries (host)
+  bool div = false, conj = false;
+};
+
+struct Ilu0 {
+  int64_t n = 0, nnz = 0;
+  int C = 1, KF = 1;
+  int flags = 0;
+  const int32_t *row_ptr = nullptr, *col_idx = nullptr;
+  int32_t *diag = nullptr;     // [n]
+  double *f = nullptr;         // [nnz * C * KF] factor in A's pattern
+  Plan L, U, UH, LH;
+  double *tmp = nullptr;       // [n * C * 4] intermediate of an apply
+  int32_t *words = nullptr;    // device: [0] abort of standalone applies,
+                               // [1] zero-pivot row, [2] non-finite row
+};
+
+// Host launchers shared by the C-ABI and the solvers (ops.hip).
+size_t ilu0_layout(int64_t n, int64_t nnz, int C, int KF, int flags, Bump &b, Ilu0 *M);
+int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     Ilu0 *M, mpk_info *info, hipStream_t s);
+int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z,
+                      int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
+                      hipStream_t s);
+int spmv_launch(int C, int K, int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                const double *x, double *y, const int32_t *done, hipStream_t s);
+int validate_csr_args(const mpk_csr *A);
+int csr_check_device_values(const mpk_csr *A, int C, int32_t *word, int64_t *bad_row,
+                            hipStream_t s);
+inline unsigned nblocks(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
+double now_ms();
+
+// Launch error check for host code.
+#define MPK_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return MPK_EDEVICE;          \
+  } while (0)
+
+template <class F> int dispatch_ck(int C, int K, F &&f) {
+  switch (C * 10 + K) {
+    case 11: return f.template operator()<1, 1>();
+    case 12: return f.template operator()<1, 2>();
+    case 13: return f.template operator()<1, 3>();
+    case 14: return f.template operator()<1, 4>();
+    case 21: return f.template operator()<2, 1>();
+    case 22: return f.template operator()<2, 2>();
+    case 23: return f.template operator()<2, 3>();
+    case 24: return f.template operator()<2, 4>();
+  }
+  return MPK_EINVAL;
+}
+
+// Host-side CSR checks and schedules (analysis.cpp).
+struct HostCsr {
+  int64_t n = 0, nnz = 0;
+  std::vector<int32_t> rp, ci;
+};
+int fetch_pattern(const mpk_csr *A, HostCsr &h, hipStream_t s);
+int check_pattern(const HostCsr &h, int64_t *bad_row);
+void host_diag(const HostCsr &h, std::vector<int32_t> &diag);
+
+struct HostPlan {
+  std::vector<int32_t> order, ptr, col, src, dsrc, seg, levptr;
+  int32_t nlev = 0;
+};
+// kind: 0 = L (strict lower of rows, forward), 1 = U (strict upper, backward,
+// divides), 2 = U^H (columns of the upper part, forward, divides),
+// 3 = L^H (columns of the strict lower part, backward).
+void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, HostPlan &p);
+size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out);
+int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);
+
+// Transposed pattern with source map (for A^T / A^H products).
+void host_transpose(const HostCsr &h, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
+                    std::vector<int32_t> &tsrc);
+
+}  // namespace mpk

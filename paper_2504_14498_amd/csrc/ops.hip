@@ -1,0 +1,374 @@
+// ops.hip -- SpMV, inner product and ILU(0) (factor, apply) behind the
+// C-ABI declared in include/mpk.h.
+#include <chrono>
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace mpk {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+int validate_csr_args(const mpk_csr *A) {
+  if (!A || A->n <= 0 || A->nnz < A->n || A->nnz >= (int64_t(1) << 31) || A->n >= (int64_t(1) << 31))
+    return MPK_EINVAL;
+  if (!A->row_ptr || !A->col_idx || !A->val) return MPK_EINVAL;
+  return MPK_OK;
+}
+
+int csr_check_device_values(const mpk_csr *A, int C, int32_t *word, int64_t *bad_row,
+                            hipStream_t s) {
+  int32_t init = INT_MAX, got = INT_MAX;
+  MPK_HIP(hipMemcpyAsync(word, &init, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(check_finite, dim3(nblocks(A->n)), dim3(BLOCK), 0, s, A->n, C, A->row_ptr,
+                     A->val, word);
+  MPK_HIP(hipGetLastError());
+  MPK_HIP(hipMemcpyAsync(&got, word, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  if (got != INT_MAX) {
+    *bad_row = got;
+    return MPK_ENONFINITE;
+  }
+  return MPK_OK;
+}
+
+int spmv_launch(int C, int K, int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                const double *x, double *y, const int32_t *done, hipStream_t s) {
+  if (n == 0) return MPK_OK;
+  return dispatch_ck(C, K, [&]<int CC, int KK>() {
+    SpmvOp<CC, KK> op{rp, ci, val, x, y};
+    hipLaunchKernelGGL((row_kernel<CC, KK, 0, SpmvOp<CC, KK>>), dim3(nblocks(n)), dim3(BLOCK), 0,
+                       s, n, op, done, (double *)nullptr);
+    return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
+  });
+}
+
+// ------------------------------------------------------------- ILU(0)
+size_t ilu0_layout(int64_t n, int64_t nnz, int C, int KF, int flags, Bump &b, Ilu0 *M) {
+  Ilu0 tmp;
+  Ilu0 &m = M ? *M : tmp;
+  m.words = b.take<int32_t>(64);
+  m.diag = b.take<int32_t>(size_t(n));
+  m.f = b.take<double>(size_t(nnz) * C * KF);
+  plan_bytes(n, nnz, C, KF, false, b, &m.L);
+  plan_bytes(n, nnz, C, KF, true, b, &m.U);
+  if (flags & MPK_ILU0_ADJOINT) {
+    plan_bytes(n, nnz, C, KF, true, b, &m.UH);
+    plan_bytes(n, nnz, C, KF, false, b, &m.LH);
+  }
+  m.tmp = b.take<double>(size_t(n) * C * 4);
+  return b.off;
+}
+
+template <int C, int KF>
+static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
+  const Plan &L = M.L;
+  for (int32_t l = 0; l < L.nlev; ++l) {
+    const int32_t a = L.h_levptr[l], cnt = L.h_levptr[l + 1] - a;
+    hipLaunchKernelGGL((ilu0_level<C, KF>), dim3(nblocks(cnt)), dim3(BLOCK), 0, s, cnt,
+                       L.order + a, M.row_ptr, M.col_idx, M.diag, M.f, M.words + 1);
+  }
+  MPK_HIP(hipGetLastError());
+  return MPK_OK;
+}
+
+static int gather_plan(const Plan &P, const Ilu0 &M, hipStream_t s) {
+  if (P.nnz > 0)
+    hipLaunchKernelGGL(gather_vals, dim3(nblocks(P.nnz)), dim3(BLOCK), 0, s, P.nnz, M.C, M.KF,
+                       P.src, M.f, P.val, 0);
+  if (P.div)
+    hipLaunchKernelGGL(gather_vals, dim3(nblocks(P.n)), dim3(BLOCK), 0, s, P.n, M.C, M.KF, P.dsrc,
+                       M.f, P.dval, 0);
+  MPK_HIP(hipGetLastError());
+  return MPK_OK;
+}
+
+int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     Ilu0 *M, mpk_info *info, hipStream_t s) {
+  const double t0 = now_ms();
+  int64_t bad = -1;
+  if (info) info->bad_row = -1;
+  Bump b(ws);
+  if (ilu0_layout(A->n, A->nnz, C, KF, flags, b, M) > ws_bytes) return MPK_EWORKSPACE;
+  M->n = A->n;
+  M->nnz = A->nnz;
+  M->C = C;
+  M->KF = KF;
+  M->flags = flags;
+  M->row_ptr = A->row_ptr;
+  M->col_idx = A->col_idx;
+  HostCsr h;
+  int st = fetch_pattern(A, h, s);
+  if (st) return st;
+  st = check_pattern(h, &bad);
+  if (st) {
+    if (info) info->bad_row = bad;
+    return st;
+  }
+  st = csr_check_device_values(A, C, M->words + 2, &bad, s);
+  if (st) {
+    if (info) info->bad_row = bad;
+    return st;
+  }
+  std::vector<int32_t> diag;
+  host_diag(h, diag);
+  HostPlan hp[4];
+  build_plan(h, diag, 0, hp[0]);
+  build_plan(h, diag, 1, hp[1]);
+  if (flags & MPK_ILU0_ADJOINT) {
+    build_plan(h, diag, 2, hp[2]);
+    build_plan(h, diag, 3, hp[3]);
+  }
+  MPK_HIP(hipMemcpyAsync(M->diag, diag.data(), sizeof(int32_t) * A->n, hipMemcpyHostToDevice, s));
+  if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
+  M->U.div = true;
+  M->L.div = false;
+  if (flags & MPK_ILU0_ADJOINT) {
+    if ((st = upload_plan(hp[2], M->UH, s)) || (st = upload_plan(hp[3], M->LH, s))) return st;
+    M->UH.div = true;
+    M->LH.div = false;
+    M->UH.conj = M->LH.conj = true;
+  }
+  int32_t init[3] = {0, INT_MAX, INT_MAX};
+  MPK_HIP(hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(promote_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, KF, A->val,
+                     M->f);
+  MPK_HIP(hipGetLastError());
+  st = (C == 1 ? (KF == 1 ? ilu0_levels<1, 1>(*M, s) : ilu0_levels<1, 2>(*M, s))
+               : (KF == 1 ? ilu0_levels<2, 1>(*M, s) : ilu0_levels<2, 2>(*M, s)));
+  if (st) return st;
+  int32_t badpiv = INT_MAX;
+  MPK_HIP(hipMemcpyAsync(&badpiv, M->words + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  if (badpiv != INT_MAX) {
+    if (info) info->bad_row = badpiv;
+    return MPK_EZERO_PIVOT;
+  }
+  if ((st = gather_plan(M->L, *M, s)) || (st = gather_plan(M->U, *M, s))) return st;
+  if (flags & MPK_ILU0_ADJOINT)
+    if ((st = gather_plan(M->UH, *M, s)) || (st = gather_plan(M->LH, *M, s))) return st;
+  MPK_HIP(hipStreamSynchronize(s));
+  if (info) info->setup_ms = now_ms() - t0;
+  return MPK_OK;
+}
+
+template <int C, int K, int KF, bool DIV, bool CONJ>
+static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *abort_flag,
+                        const int32_t *done, hipStream_t s) {
+  const unsigned grid = unsigned(std::min<int64_t>((P.nseg + 3) / 4, 2048));
+  hipLaunchKernelGGL((trsv_syncfree<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK), 0,
+                     s, P.order, P.ptr, P.col, P.val, P.dval, P.seg, P.nseg, rhs, out, P.sync,
+                     abort_flag, done);
+}
+
+template <int C, int K, int KF>
+static int apply_ckf(const Ilu0 &M, int conj, const double *r, double *z, int32_t *abort_reset,
+                     int32_t *abort_flag, const int32_t *done, hipStream_t s) {
+  const Plan &P1 = conj ? M.UH : M.L;
+  const Plan &P2 = conj ? M.LH : M.U;
+  const int64_t words = M.n * C * K;
+  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(words)), dim3(BLOCK), 0, s, words, M.tmp, z, P1.sync,
+                     P2.sync, abort_reset, done);
+  if (!conj) {
+    launch_trsv<C, K, KF, false, false>(P1, r, M.tmp, abort_flag, done, s);
+    launch_trsv<C, K, KF, true, false>(P2, M.tmp, z, abort_flag, done, s);
+  } else {
+    launch_trsv<C, K, KF, true, true>(P1, r, M.tmp, abort_flag, done, s);
+    launch_trsv<C, K, KF, false, true>(P2, M.tmp, z, abort_flag, done, s);
+  }
+  return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
+}
+
+int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z,
+                      int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
+                      hipStream_t s) {
+  if (K < M.KF || K < 1 || K > 4) return MPK_EUNSUPPORTED;
+  if (conj && !(M.flags & MPK_ILU0_ADJOINT)) return MPK_EUNSUPPORTED;
+  return dispatch_ck(M.C, K, [&]<int C, int KK>() {
+    if constexpr (KK >= 2) {
+      if (M.KF == 2) return apply_ckf<C, KK, 2>(M, conj, r, z, abort_reset, abort_flag, done, s);
+    }
+    return apply_ckf<C, KK, 1>(M, conj, r, z, abort_reset, abort_flag, done, s);
+  });
+}
+
+// --------------------------------------------------------------- dots
+template <int C, int K> struct DotOp {
+  const double *a, *b;
+  __device__ void operator()(int64_t i, el<C, K> *d) const {
+    d[0] = el_cdot_term<C, K>(el_load<C, K>(a + size_t(i) * C * K),
+                              el_load<C, K>(b + size_t(i) * C * K));
+  }
+};
+
+template <int C, int K>
+__global__ __launch_bounds__(BLOCK) void dot_final(const double *partials, int nblk, double *out) {
+  el<C, K> tot[1];
+  reduce_partials<C, K, 1>(partials, nblk, tot);
+  if (threadIdx.x == 0) el_store<C, K>(out, tot[0]);
+}
+
+}  // namespace mpk
+
+using namespace mpk;
+
+extern "C" {
+
+const char *mpk_status_str(int status) {
+  switch (status) {
+    case MPK_OK: return "ok";
+    case MPK_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case MPK_BREAKDOWN: return "breakdown (a method scalar became zero)";
+    case MPK_EINVAL: return "invalid argument";
+    case MPK_EDEVICE: return "HIP runtime error";
+    case MPK_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case MPK_EZERO_PIVOT: return "zero pivot in ILU(0)";
+    case MPK_ENO_DIAG: return "diagonal entry not stored";
+    case MPK_EUNSUPPORTED: return "unsupported combination";
+    case MPK_ENONFINITE: return "non-finite matrix entry";
+    case MPK_EPATTERN: return "CSR pattern not strictly ascending or out of range";
+    case MPK_EWATCHDOG: return "device dependency wait exceeded its bound";
+  }
+  return "unknown status";
+}
+
+int mpk_version(void) { return 100; }
+
+size_t mpk_spmv_workspace_bytes(const mpk_csr *A, int is_complex, int trans) {
+  if (!A || A->n <= 0 || A->nnz < 0) return 0;
+  if (!trans) return 0;
+  Bump b(nullptr);
+  b.take<int32_t>(size_t(A->n) + 1);
+  b.take<int32_t>(size_t(A->nnz));
+  b.take<int32_t>(size_t(A->nnz));
+  b.take<double>(size_t(A->nnz) * (is_complex ? 2 : 1));
+  return b.off;
+}
+
+static int csr_spmv(int C, mpk_prec xp, const mpk_csr *A, int trans, const double *x, double *y,
+                    void *ws, size_t ws_bytes, void *stream) {
+  int st = validate_csr_args(A);
+  if (st) return st;
+  if (xp < MPK_D || xp > MPK_QD || !x || !y) return MPK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (!trans) return spmv_launch(C, int(xp), A->n, A->row_ptr, A->col_idx, A->val, x, y, nullptr, s);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
+      ws_bytes < mpk_spmv_workspace_bytes(A, C == 2, 1))
+    return MPK_EWORKSPACE;
+  HostCsr h;
+  if ((st = fetch_pattern(A, h, s))) return st;
+  int64_t bad;
+  if ((st = check_pattern(h, &bad))) return st;
+  std::vector<int32_t> trp, tci, tsrc;
+  host_transpose(h, trp, tci, tsrc);
+  Bump b(ws);
+  int32_t *d_rp = b.take<int32_t>(size_t(A->n) + 1), *d_ci = b.take<int32_t>(size_t(A->nnz)),
+          *d_src = b.take<int32_t>(size_t(A->nnz));
+  double *d_val = b.take<double>(size_t(A->nnz) * C);
+  MPK_HIP(hipMemcpyAsync(d_rp, trp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice, s));
+  MPK_HIP(hipMemcpyAsync(d_ci, tci.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));
+  MPK_HIP(hipMemcpyAsync(d_src, tsrc.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(gather_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, 1, d_src,
+                     A->val, d_val, C == 2 ? 1 : 0);
+  MPK_HIP(hipGetLastError());
+  st = spmv_launch(C, int(xp), A->n, d_rp, d_ci, d_val, x, y, nullptr, s);
+  MPK_HIP(hipStreamSynchronize(s));
+  return st;
+}
+
+int mpk_dcsr_spmv(mpk_prec xp, const mpk_csr *A, int trans, const double *x, double *y, void *ws,
+                  size_t ws_bytes, void *stream) {
+  return csr_spmv(1, xp, A, trans, x, y, ws, ws_bytes, stream);
+}
+
+int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x, double *y,
+                  void *ws, size_t ws_bytes, void *stream) {
+  return csr_spmv(2, xp, A, conj_trans, x, y, ws, ws_bytes, stream);
+}
+
+size_t mpk_ilu0_workspace_bytes(const mpk_csr *A, mpk_prec fp, int is_complex, int flags) {
+  if (!A || A->n <= 0 || A->nnz < 0 || (fp != MPK_D && fp != MPK_DD)) return 0;
+  Bump b(nullptr);
+  return ilu0_layout(A->n, A->nnz, is_complex ? 2 : 1, int(fp), flags, b, nullptr);
+}
+
+static int ilu0_factor(int C, mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                       mpk_ilu0 **M, mpk_info *info, void *stream) {
+  int st = validate_csr_args(A);
+  if (st) return st;
+  if ((fp != MPK_D && fp != MPK_DD) || !M || (flags & ~MPK_ILU0_ADJOINT)) return MPK_EINVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
+      ws_bytes < mpk_ilu0_workspace_bytes(A, fp, C == 2, flags))
+    return MPK_EWORKSPACE;
+  Ilu0 *h = new Ilu0();
+  st = ilu0_factor_impl(C, int(fp), A, flags, ws, ws_bytes, h, info, (hipStream_t)stream);
+  if (info) info->status = st;
+  if (st) {
+    delete h;
+    *M = nullptr;
+    return st;
+  }
+  *M = reinterpret_cast<mpk_ilu0 *>(h);
+  return MPK_OK;
+}
+
+int mpk_dilu0_factor(mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     mpk_ilu0 **M, mpk_info *info, void *stream) {
+  return ilu0_factor(1, fp, A, flags, ws, ws_bytes, M, info, stream);
+}
+
+int mpk_zilu0_factor(mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
+                     mpk_ilu0 **M, mpk_info *info, void *stream) {
+  return ilu0_factor(2, fp, A, flags, ws, ws_bytes, M, info, stream);
+}
+
+static int ilu0_apply(int C, const mpk_ilu0 *Mh, mpk_prec vp, int conj_trans, const double *r,
+                      double *z, void *stream) {
+  const Ilu0 *M = reinterpret_cast<const Ilu0 *>(Mh);
+  if (!M || !r || !z || M->C != C || vp < MPK_D || vp > MPK_QD) return MPK_EINVAL;
+  return ilu0_apply_launch(*M, int(vp), conj_trans ? 1 : 0, r, z, M->words, M->words,
+                           nullptr, (hipStream_t)stream);
+}
+
+int mpk_dilu0_apply(const mpk_ilu0 *M, mpk_prec vp, int conj_trans, const double *r, double *z,
+                    void *stream) {
+  return ilu0_apply(1, M, vp, conj_trans, r, z, stream);
+}
+
+int mpk_zilu0_apply(const mpk_ilu0 *M, mpk_prec vp, int conj_trans, const double *r, double *z,
+                    void *stream) {
+  return ilu0_apply(2, M, vp, conj_trans, r, z, stream);
+}
+
+void mpk_ilu0_destroy(mpk_ilu0 *M) { delete reinterpret_cast<Ilu0 *>(M); }
+
+size_t mpk_dot_workspace_bytes(int64_t n, int is_complex, mpk_prec p) {
+  if (n <= 0 || p < MPK_D || p > MPK_QD) return 0;
+  Bump b(nullptr);
+  b.take<double>(size_t(nblocks(n)) * (is_complex ? 2 : 1) * int(p));
+  return b.off;
+}
+
+int mpk_dot(mpk_prec p, int is_complex, int64_t n, const double *a, const double *b, double *out,
+            void *ws, size_t ws_bytes, void *stream) {
+  if (n <= 0 || p < MPK_D || p > MPK_QD || !a || !b || !out) return MPK_EINVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
+      ws_bytes < mpk_dot_workspace_bytes(n, is_complex, p))
+    return MPK_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  double *part = static_cast<double *>(ws);
+  const int nb = int(nblocks(n));
+  return dispatch_ck(is_complex ? 2 : 1, int(p), [&]<int C, int K>() {
+    DotOp<C, K> op{a, b};
+    hipLaunchKernelGGL((row_kernel<C, K, 1, DotOp<C, K>>), dim3(nb), dim3(BLOCK), 0, s, n, op,
+                       (const int32_t *)nullptr, part);
+    hipLaunchKernelGGL((dot_final<C, K>), dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
+                       out);
+    return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""Thin Python binding of libmpk.so (the C-ABI in include/mpk.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory and streams.  Vectors are float64
+CUDA tensors of shape (n, C, K): C = 1 real / 2 complex, K limbs (1 D, 2 DD,
+3 TD, 4 QD), leading limb first.  There is no CPU fallback: if the library
+is not built, loading raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpk.so")
+
+METHODS = {"bicg": 0, "cgs": 1, "bicgstab": 2, "gpbicg": 3}
+STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval", -2: "edevice",
+          -3: "eworkspace", -4: "ezero_pivot", -5: "eno_diag", -6: "eunsupported",
+          -7: "enonfinite", -8: "epattern", -9: "ewatchdog"}
+ILU0_ADJOINT = 1
+
+
+class MpkError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, _lib().mpk_status_str(status).decode(), status))
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("bad_row", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("relres_recursive", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("res_history", ctypes.c_void_p),
+                ("res_history_len", ctypes.c_int64)]
+
+
+_L = None
+
+# (name, restype, argtypes) of every exported entry point
+_P, _I, _S, _D, _I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double, ctypes.c_int64
+_CSRP = ctypes.POINTER(_Csr)
+_INFOP = ctypes.POINTER(_Info)
+SIGNATURES = [
+    ("mpk_status_str", ctypes.c_char_p, [_I]),
+    ("mpk_version", _I, []),
+    ("mpk_spmv_workspace_bytes", _S, [_CSRP, _I, _I]),
+    ("mpk_dcsr_spmv", _I, [_I, _CSRP, _I, _P, _P, _P, _S, _P]),
+    ("mpk_zcsr_spmv", _I, [_I, _CSRP, _I, _P, _P, _P, _S, _P]),
+    ("mpk_ilu0_workspace_bytes", _S, [_CSRP, _I, _I, _I]),
+    ("mpk_dilu0_factor", _I, [_I, _CSRP, _I, _P, _S, ctypes.POINTER(_P), _INFOP, _P]),
+    ("mpk_zilu0_factor", _I, [_I, _CSRP, _I, _P, _S, ctypes.POINTER(_P), _INFOP, _P]),
+    ("mpk_dilu0_apply", _I, [_P, _I, _I, _P, _P, _P]),
+    ("mpk_zilu0_apply", _I, [_P, _I, _I, _P, _P, _P]),
+    ("mpk_ilu0_destroy", None, [_P]),
+    ("mpk_krylov_workspace_bytes", _S, [_I, _I, _I, _CSRP, _I]),
+    ("mpk_dkrylov_solve", _I, [_I, _I, _I, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP, _P]),
+    ("mpk_zkrylov_solve", _I, [_I, _I, _I, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP, _P]),
+    ("mpk_dot_workspace_bytes", _S, [_I64, _I, _I]),
+    ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
+]
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmpk.so is not built (run __graft_entry__.build() or "
+                              "python paper_2504_14498_amd/build.py): " + LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _L = L
+    return _L
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(st, what):
+    if st < 0:
+        raise MpkError(st, what)
+    return st
+
+
+def _workspace(nbytes, device):
+    # 256-byte aligned device buffer owned by torch
+    nbytes = max(int(nbytes), 1)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, nbytes
+
+
+class Csr:
+    """CSR matrix on the device: row_ptr/col_idx int32, val float64 (nnz,)
+    real or (nnz, 2) complex."""
+
+    def __init__(self, row_ptr, col_idx, val, device="cuda"):
+        self.row_ptr = torch.as_tensor(np.asarray(row_ptr), dtype=torch.int32).to(device)
+        self.col_idx = torch.as_tensor(np.asarray(col_idx), dtype=torch.int32).to(device)
+        v = torch.as_tensor(np.asarray(val), dtype=torch.float64).to(device)
+        self.is_complex = v.dim() == 2
+        self.val = v.contiguous()
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col_idx.numel()
+        self.device = self.val.device
+        self.c = _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                      self.val.data_ptr())
+
+    @property
+    def C(self):
+        return 2 if self.is_complex else 1
+
+    @classmethod
+    def from_problem(cls, p, device="cuda"):
+        return cls(p.row_ptr, p.col_idx, p.val, device)
+
+
+def _vec_check(A, v, name):
+    if v.dtype != torch.float64 or not v.is_cuda or v.dim() != 3 or v.shape[0] != A.n \
+            or v.shape[1] != A.C or not v.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 CUDA tensor of shape (n, C, K)" % name)
+    return v.shape[2]
+
+
+def csr_spmv(A, x, y=None, trans=False, stream=None):
+    """y = A x (or A^T x / A^H x)."""
+    K = _vec_check(A, x, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    fn = _lib().mpk_zcsr_spmv if A.is_complex else _lib().mpk_dcsr_spmv
+    ws = None
+    ws_ptr, ws_n = 0, 0
+    if trans:
+        nb = _lib().mpk_spmv_workspace_bytes(ctypes.byref(A.c), int(A.is_complex), 1)
+        ws, ws_ptr, ws_n = _workspace(nb, A.device)
+    _check(fn(K, ctypes.byref(A.c), int(trans), _ptr(x), _ptr(y), ctypes.c_void_p(ws_ptr), ws_n,
+              _stream(stream)), "csr_spmv")
+    return y
+
+
+class Ilu0:
+    """ILU(0) factor held in a torch-owned device workspace."""
+
+    def __init__(self, A, handle, ws, fprec, adjoint):
+        self.A = A
+        self.handle = handle
+        self._ws = ws
+        self.fprec = fprec
+        self.adjoint = adjoint
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _L is not None:
+            _L.mpk_ilu0_destroy(self.handle)
+            self.handle = None
+
+
+def ilu0_factor(A, fprec=1, adjoint=False, stream=None):
+    """ILU(0) factorisation in binary64 (fprec=1) or double-double (2)."""
+    flags = ILU0_ADJOINT if adjoint else 0
+    nb = _lib().mpk_ilu0_workspace_bytes(ctypes.byref(A.c), fprec, int(A.is_complex), flags)
+    if nb == 0:
+        raise ValueError("bad ILU(0) arguments")
+    ws, ws_ptr, ws_n = _workspace(nb, A.device)
+    h = ctypes.c_void_p()
+    info = _Info()
+    fn = _lib().mpk_zilu0_factor if A.is_complex else _lib().mpk_dilu0_factor
+    st = fn(fprec, ctypes.byref(A.c), flags, ctypes.c_void_p(ws_ptr), ws_n, ctypes.byref(h),
+            ctypes.byref(info), _stream(stream))
+    if st < 0:
+        e = MpkError(st, "ilu0_factor")
+        e.bad_row = info.bad_row
+        raise e
+    return Ilu0(A, h, ws, fprec, adjoint)
+
+
+def ilu0_apply(M, r, z=None, conj_trans=False, stream=None):
+    """z = M^{-1} r (or M^{-H} r)."""
+    K = _vec_check(M.A, r, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    fn = _lib().mpk_zilu0_apply if M.A.is_complex else _lib().mpk_dilu0_apply
+    _check(fn(M.handle, K, int(conj_trans), _ptr(r), _ptr(z), _stream(stream)), "ilu0_apply")
+    return z
+
+
+def dot(a, b, stream=None):
+    """<a, b> = sum conj(a_i) b_i in the working precision: tensor (C, K)."""
+    n, C, K = a.shape
+    out = torch.empty((C, K), dtype=torch.float64, device=a.device)
+    nb = _lib().mpk_dot_workspace_bytes(n, int(C == 2), K)
+    ws, ws_ptr, ws_n = _workspace(nb, a.device)
+    _check(_lib().mpk_dot(K, int(C == 2), n, _ptr(a), _ptr(b), _ptr(out), ctypes.c_void_p(ws_ptr),
+                          ws_n, _stream(stream)), "dot")
+    return out
+
+
+_SIDE = {}
+
+
+def _side_stream(device):
+    if device not in _SIDE:
+        _SIDE[device] = torch.cuda.Stream(device=device)
+    return _SIDE[device]
+
+
+def krylov_workspace_bytes(method, A, vprec, fprec):
+    return _lib().mpk_krylov_workspace_bytes(METHODS[method], vprec, fprec, ctypes.byref(A.c),
+                                             int(A.is_complex))
+
+
+def krylov_solve(method, A, b, x0=None, fprec=1, tol_rel=1e-25, tol_abs=0.0, max_iter=1000,
+                 hist_len=0, workspace=None, graph=True):
+    """Solve A x = b.  b: (n, C, K) float64 CUDA tensor; fprec 0 = no
+    preconditioner, 1 = binary64 ILU(0), 2 = double-double ILU(0).
+    Returns (x, info dict).  graph=True runs on a side stream so that each
+    pass is replayed from a captured hipGraph."""
+    K = _vec_check(A, b, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    nb = krylov_workspace_bytes(method, A, K, fprec)
+    if nb == 0:
+        raise ValueError("bad krylov_solve arguments")
+    if workspace is None or workspace[2] < nb:
+        workspace = _workspace(nb, A.device)
+    ws, ws_ptr, ws_n = workspace
+    hist = torch.zeros(max(hist_len, 1), dtype=torch.float64, device=A.device)
+    info = _Info()
+    info.res_history = hist.data_ptr() if hist_len > 0 else None
+    info.res_history_len = hist_len
+    fn = _lib().mpk_zkrylov_solve if A.is_complex else _lib().mpk_dkrylov_solve
+    cur = torch.cuda.current_stream(A.device)
+    s = _side_stream(A.device) if graph else cur
+    if graph:
+        s.wait_stream(cur)
+    st = fn(METHODS[method], K, fprec, float(tol_rel), float(tol_abs), int(max_iter),
+            ctypes.byref(A.c), _ptr(b), _ptr(x), ctypes.c_void_p(ws_ptr), ws_n, ctypes.byref(info),
+            ctypes.c_void_p(s.cuda_stream))
+    if graph:
+        cur.wait_stream(s)
+    if st < 0:
+        e = MpkError(st, "krylov_solve")
+        e.bad_row = info.bad_row
+        raise e
+    out = {"status": STATUS.get(st, st), "code": st, "iters": info.iters,
+           "relres_recursive": info.relres_recursive, "relres_true": info.relres_true,
+           "setup_ms": info.setup_ms, "solve_ms": info.solve_ms, "bad_row": info.bad_row,
+           "hist": hist[: min(hist_len, info.iters)] if hist_len else None,
+           "workspace": workspace}
+    return x, out

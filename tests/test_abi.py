@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/mpk.h, and rejects invalid arguments before any device
+work (so these calls are safe on a host without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_14498_amd import mpk
+    return mpk.library()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mpk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpk_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2504_14498_amd import mpk
+    bound = {name for name, _, _ in mpk.SIGNATURES}
+    assert set(declared_functions()) <= bound
+
+
+def test_status_strings(lib):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+        s = lib.mpk_status_str(code).decode()
+        assert s and s != "unknown status"
+    assert lib.mpk_version() >= 100
+
+
+def _csr(n, nnz, rp=1, ci=1, val=1):
+    from paper_2504_14498_amd import mpk
+    return mpk._Csr(n, nnz, rp, ci, val)
+
+
+def test_invalid_arguments_rejected_before_device_work(lib):
+    from paper_2504_14498_amd import mpk
+    info = mpk._Info()
+    ws = ctypes.c_void_p(256)
+    # null matrix
+    assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, None, ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, 1 << 30, ctypes.byref(info), None) == -1
+    # n <= 0, nnz < n, null pointers
+    for A in (_csr(0, 0), _csr(4, 3), _csr(4, 4, rp=0), _csr(4, 4, ci=0), _csr(4, 4, val=0)):
+        assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                     ctypes.c_void_p(8), ws, 1 << 30, ctypes.byref(info),
+                                     None) == -1
+    A = _csr(4, 4)
+    # bad method / precision / factor precision above the vector precision
+    assert lib.mpk_dkrylov_solve(7, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, 1 << 30, None, None) == -1
+    assert lib.mpk_dkrylov_solve(2, 5, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, 1 << 30, None, None) == -1
+    assert lib.mpk_dkrylov_solve(2, 1, 2, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, 1 << 30, None, None) == -1
+    assert lib.mpk_dkrylov_solve(2, 2, 3, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, 1 << 30, None, None) == -1
+    # negative tolerance, NaN tolerance, negative max_iter
+    for tol, mi in ((-1.0, 10), (float("nan"), 10), (1e-25, -1)):
+        assert lib.mpk_dkrylov_solve(2, 2, 1, tol, 0.0, mi, ctypes.byref(A), ctypes.c_void_p(8),
+                                     ctypes.c_void_p(8), ws, 1 << 30, None, None) == -1
+    # workspace missing, misaligned, too small
+    need = lib.mpk_krylov_workspace_bytes(2, 2, 1, ctypes.byref(A), 0)
+    assert need > 0
+    assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), None, need, None, None) == -3
+    assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ctypes.c_void_p(264), need, None, None) == -3
+    assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), ws, need - 1, None, None) == -3
+    # ILU(0): factor precision must be D or DD
+    h = ctypes.c_void_p()
+    assert lib.mpk_dilu0_factor(3, ctypes.byref(A), 0, ws, 1 << 30, ctypes.byref(h), None,
+                                None) == -1
+    assert lib.mpk_dilu0_factor(1, ctypes.byref(A), 4, ws, 1 << 30, ctypes.byref(h), None,
+                                None) == -1
+    assert lib.mpk_dilu0_apply(None, 2, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == -1
+    # SpMV: precision out of range, null vectors
+    assert lib.mpk_dcsr_spmv(0, ctypes.byref(A), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None,
+                             0, None) == -1
+    assert lib.mpk_dcsr_spmv(2, ctypes.byref(A), 0, None, ctypes.c_void_p(8), None, 0, None) == -1
+    assert lib.mpk_dot(2, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), ws,
+                       1 << 20, None) == -1
+
+
+def test_workspace_queries_scale(lib):
+    from paper_2504_14498_amd import mpk
+    small, big = _csr(1000, 5000), _csr(100000, 500000)
+    for m in range(4):
+        for vp in (1, 2, 3, 4):
+            for fp in (0, 1, 2):
+                a = lib.mpk_krylov_workspace_bytes(m, vp, fp, ctypes.byref(small), 0)
+                b = lib.mpk_krylov_workspace_bytes(m, vp, fp, ctypes.byref(big), 1)
+                assert 0 < a < b
+                # vectors alone: at least 8 vectors of n C K doubles
+                assert b >= 8 * 100000 * 2 * vp * 8
+    assert lib.mpk_krylov_workspace_bytes(9, 2, 1, ctypes.byref(small), 0) == 0
+    assert lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 3, 0, 0) == 0
+    assert lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 1, 0, 1) > \
+        lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 1, 0, 0)
+    assert lib.mpk_spmv_workspace_bytes(ctypes.byref(small), 0, 0) == 0
+    assert lib.mpk_spmv_workspace_bytes(ctypes.byref(small), 1, 1) > 5000 * 16
+    assert lib.mpk_dot_workspace_bytes(1000, 0, 2) >= 4 * 2 * 8

@@ -77,10 +77,23 @@ struct Plan {
   int32_t *src = nullptr;      // [nnz] index of the value in A's pattern
   int32_t *dsrc = nullptr;     // [n] diagonal position (division plans)
   int32_t *seg = nullptr;      // [nseg+1] first position of each segment
+  int32_t *seg_level = nullptr;  // [nseg] level of each segment
+  int32_t *lev_size = nullptr;   // [nlev] rows per level
+  int32_t *lev_done = nullptr;   // [nlev] rows of each level finished (per sweep)
   double *val = nullptr;       // [nnz * C * KF] gathered factor values
   double *dval = nullptr;      // [n * C * KF] gathered pivots
   int32_t *sync = nullptr;     // [0] ticket, [1] watchdog abort
+  // blocked schedule (mode 1): contiguous row blocks in processing order,
+  // each with its own local levels; positions are block-major
+  int32_t mode = 0;            // 0 level schedule, 1 blocked schedule
+  int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
+  int32_t blk_rows = 0;        // rows per block
+  int32_t *blk_r = nullptr;    // [2*nblk] row range [r0, r1) of each block
+  int32_t *blk_lev = nullptr;  // [nblk+1] first local level of each block
+  int32_t *loc_pos = nullptr;  // [nloc+1] first position of each local level
+  std::vector<int32_t> h_blk;  // host copies kept alive for the uploads
   std::vector<int32_t> h_levptr;   // level boundaries (host)
+  std::vector<int32_t> h_levsize;  // level sizes (host copy kept alive for the upload)
   bool div = false, conj = false;
 };
 
@@ -93,6 +106,8 @@ struct Ilu0 {
   double *f = nullptr;         // [nnz * C * KF] factor in A's pattern
   Plan L, U, UH, LH;
   double *tmp = nullptr;       // [n * C * 4] intermediate of an apply
+  int32_t *fac_order = nullptr;  // [n] rows by global forward level (factorisation)
+  std::vector<int32_t> h_fac_levptr;
   int32_t *words = nullptr;    // device: [0] abort of standalone applies,
                                // [1] zero-pivot row, [2] non-finite row
 };
@@ -143,13 +158,18 @@ int check_pattern(const HostCsr &h, int64_t *bad_row);
 void host_diag(const HostCsr &h, std::vector<int32_t> &diag);
 
 struct HostPlan {
-  std::vector<int32_t> order, ptr, col, src, dsrc, seg, levptr;
+  std::vector<int32_t> order, ptr, col, src, dsrc, seg, seg_level, levptr;
   int32_t nlev = 0;
+  int32_t mode = 0, nblk = 0, blk_rows = 0;
+  std::vector<int32_t> blk_r, blk_lev, loc_pos;
+  std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)
 };
 // kind: 0 = L (strict lower of rows, forward), 1 = U (strict upper, backward,
 // divides), 2 = U^H (columns of the upper part, forward, divides),
 // 3 = L^H (columns of the strict lower part, backward).
-void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, HostPlan &p);
+void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, int blk_rows,
+                HostPlan &p);
+int default_block_rows(int C);
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out);
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);
 

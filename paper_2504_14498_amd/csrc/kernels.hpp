@@ -178,16 +178,19 @@ static __global__ void promote_vals(int64_t nnz, int C, int KF, const double *__
 }
 
 // ------------------------------------------------- triangular sweeps
-// Sync-free substitution over a level schedule.  Each wavefront takes the
-// next segment (<= 64 rows of one level, so no dependencies inside it)
+// Substitution over a level schedule in one launch.  Each wavefront takes
+// the next segment (<= 64 rows of one level, so no dependencies inside it)
 // from a global ticket; segments are handed out in level order, so every
-// row a segment waits on belongs to a segment already taken by a running
-// wavefront, and the sweep always makes progress.  Results are published
-// with agent-scope relaxed stores into an output pre-filled with SENTINEL;
-// a consumer spins (agent-scope relaxed loads) until no word of y_j is the
-// sentinel.  Every spin is bounded: past the bound the wave raises the
+// level a segment waits on was taken by running wavefronts and the sweep
+// always progresses.  Before computing, lane 0 waits until every earlier
+// level is complete (per-level counters of finished rows, one polled word
+// per wavefront instead of one per row, which keeps the polling traffic
+// small).  Results are published with agent-scope relaxed stores into an
+// output pre-filled with SENTINEL, and each dependency load still spins
+// until no word of y_j is the sentinel, so a value is never read before it
+// is written.  Every wait is bounded: past the bound the wave raises the
 // abort word, every other wave leaves its waits, and the host reports
-// MPK_EWATCHDOG.  Row arithmetic: acc = rhs_i; acc -= f_p * y_col(p) for
+// MPK_EWATCHDOG.  Row arithmetic: acc = rhs_i; acc -= f_p * y_col(p) over
 // the row's entries in ascending column order; then acc / pivot when DIV.
 constexpr int SPIN_LIMIT = 1 << 22;
 
@@ -199,6 +202,9 @@ __device__ __forceinline__ void st_agent(double *p, double v) {
   unsigned long long b = __builtin_bit_cast(unsigned long long, v);
   __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), b, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_agent_i(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int C, int K>
@@ -214,15 +220,34 @@ __device__ __forceinline__ bool wait_load(const double *p, el<C, K> &v, int32_t 
         v.c[c].v[k] = __builtin_bit_cast(double, b);
       }
     if (ok) return true;
-    if ((it & 127) == 127 &&
-        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return false;
+    if ((it & 63) == 63 && ld_agent_i(abort_flag)) return false;
     if (it >= SPIN_LIMIT) {
       __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(2);
   }
+}
+
+// Lane-0 wait until levels [frontier, L) are complete; returns the new
+// frontier (or L on abort).
+__device__ __forceinline__ int32_t wait_levels(int32_t frontier, int32_t L,
+                                               const int32_t *__restrict__ lev_size,
+                                               const int32_t *lev_done, int32_t *abort_flag) {
+  int it = 0;
+  while (frontier < L) {
+    if (ld_agent_i(lev_done + frontier) >= lev_size[frontier]) {
+      ++frontier;
+      continue;
+    }
+    if ((++it & 63) == 63 && ld_agent_i(abort_flag)) return L;
+    if (it >= SPIN_LIMIT) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return L;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  return frontier;
 }
 
 template <int C, int KF, bool CONJ>
@@ -231,55 +256,332 @@ __device__ __forceinline__ void load_f(const double *__restrict__ p, double (&f)
   for (int v = 0; v < C * KF; ++v) f[v] = (CONJ && v >= KF) ? -p[v] : p[v];
 }
 
+// Dependencies are fetched in batches of up to MAXD rows: all their words
+// are requested at once (one memory round trip), and only a batch that
+// still shows a sentinel falls back to the per-value wait.
+template <int E> constexpr int trsv_maxd() { return E <= 2 ? 8 : (E <= 4 ? 4 : 2); }
+
 template <int C, int K, int KF, bool DIV, bool CONJ>
 __global__ __launch_bounds__(BLOCK) void trsv_syncfree(
     const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ col, const double *__restrict__ val,
-    const double *__restrict__ dval, const int32_t *__restrict__ seg, int32_t nseg,
-    const double *__restrict__ rhs, double *out, int32_t *ticket, int32_t *abort_flag,
-    const int32_t *done) {
+    const double *__restrict__ dval, const int32_t *__restrict__ seg,
+    const int32_t *__restrict__ seg_level, int32_t nseg, const int32_t *__restrict__ lev_size,
+    int32_t *lev_done, const double *__restrict__ rhs, double *out, int32_t *ticket,
+    int32_t *abort_flag, const int32_t *done, int32_t xcd_stride) {
   if (done && *done) return;
-  const int lane = threadIdx.x & (WAVE - 1);
+  // optional placement: only every xcd_stride-th workgroup works, which with
+  // round-robin dispatch keeps the sweep on one XCD (a placement choice only)
+  if (blockIdx.x % xcd_stride) return;
   constexpr int E = C * K;
+  constexpr int MAXD = trsv_maxd<E>();
+  constexpr int WPB = BLOCK / WAVE;  // wavefronts per workgroup
+  __shared__ int32_t group;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  int32_t frontier = 0;
   for (;;) {
-    int32_t s = 0;
-    if (lane == 0) s = atomicAdd(ticket, 1);
-    s = __shfl(s, 0, WAVE);
-    if (s >= nseg) break;
-    const int32_t pos = seg[s] + lane;
-    if (pos < seg[s + 1]) {
-      const int32_t i = order[pos];
-      el<C, K> acc = el_load<C, K>(rhs + size_t(i) * E);
-      const int32_t pe = ptr[pos + 1];
-      for (int32_t p = ptr[pos]; p < pe; ++p) {
-        el<C, K> yj;
-        wait_load<C, K>(out + size_t(col[p]) * E, yj, abort_flag);
-        double f[C * KF];
-        load_f<C, KF, CONJ>(val + size_t(p) * C * KF, f);
-        acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, yj));
+    // one ticket per workgroup: segments group .. group+WPB-1, one per wave
+    if (threadIdx.x == 0) group = atomicAdd(ticket, WPB);
+    __syncthreads();
+    const int32_t s = group + w;
+    __syncthreads();
+    if (group >= nseg) break;
+    if (s < nseg) {
+      const int32_t L = seg_level[s];
+      const int32_t p0 = seg[s], p1 = seg[s + 1];
+      const int32_t pos = p0 + lane;
+      const bool valid = pos < p1;
+      int32_t i = 0, pb = 0, pe = 0;
+      el<C, K> acc = el_zero<C, K>();
+      int32_t cj[MAXD];
+      double fv[MAXD][C * KF];
+      if (valid) {
+        i = order[pos];
+        pb = ptr[pos];
+        pe = ptr[pos + 1];
+        acc = el_load<C, K>(rhs + size_t(i) * E);
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+          if (pb + d < pe) {
+            cj[d] = col[pb + d];
+            load_f<C, KF, CONJ>(val + size_t(pb + d) * C * KF, fv[d]);
+          }
       }
-      if constexpr (DIV) {
-        double d[C * KF];
-        load_f<C, KF, CONJ>(dval + size_t(pos) * C * KF, d);
-        acc = el_div_k<C, K, KF>(acc, d);
+      if (lane == 0) frontier = wait_levels(frontier, L, lev_size, lev_done, abort_flag);
+      frontier = __shfl(frontier, 0, WAVE);
+      if (valid) {
+        for (int32_t q0 = pb; q0 < pe; q0 += MAXD) {
+          if (q0 != pb) {
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+              if (q0 + d < pe) {
+                cj[d] = col[q0 + d];
+                load_f<C, KF, CONJ>(val + size_t(q0 + d) * C * KF, fv[d]);
+              }
+          }
+          el<C, K> yv[MAXD];
+          bool ok = true;
+#pragma unroll
+          for (int d = 0; d < MAXD; ++d) {
+            if (q0 + d < pe) {
+              const double *yp = out + size_t(cj[d]) * E;
+#pragma unroll
+              for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                  uint64_t b = ld_agent(yp + c * K + k);
+                  ok = ok && (b != SENTINEL);
+                  yv[d].c[c].v[k] = __builtin_bit_cast(double, b);
+                }
+            }
+          }
+          if (!ok) {
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+              if (q0 + d < pe) wait_load<C, K>(out + size_t(cj[d]) * E, yv[d], abort_flag);
+          }
+#pragma unroll
+          for (int d = 0; d < MAXD; ++d)
+            if (q0 + d < pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(fv[d], yv[d]));
+        }
+        if constexpr (DIV) {
+          double d[C * KF];
+          load_f<C, KF, CONJ>(dval + size_t(pos) * C * KF, d);
+          acc = el_div_k<C, K, KF>(acc, d);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            double v = acc.c[c].v[k];
+            st_agent(out + size_t(i) * E + c * K + k, v != v ? __builtin_nan("") : v);
+          }
       }
+      if (lane == 0) atomicAdd(lev_done + L, p1 - p0);
+    }
+  }
+}
+
+// Blocked schedule: a workgroup takes the next block of consecutive rows
+// (tickets hand blocks out in the sweep's order, so a block only waits on
+// blocks already taken by running workgroups) and walks the block's local
+// levels; results of the block stay in LDS for the rows of the same block
+// that need them and are published to memory (agent-scope stores) for
+// later blocks, which read them with the sentinel-checked wait.  A
+// workgroup barrier separates consecutive local levels.  Loads are
+// software-pipelined: while level l is computed from LDS, the row data,
+// factor values and external y values of level l+1 are already in flight.
+// Row arithmetic is identical to the level schedule's.
+template <int C, int K, int KF, int MAXD> struct RowPre {
+  int32_t i, pos, pb, pe;
+  bool valid;
+  el<C, K> acc;
+  int32_t cj[MAXD];
+  double f[MAXD][C * KF];
+  el<C, K> ye[MAXD];
+  bool ok;
+};
+
+// Stage 1 (several levels ahead): the row's own data and factor values.
+template <int C, int K, int KF, bool CONJ, int MAXD>
+__device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_t pos, bool valid,
+                                               const int32_t *__restrict__ order,
+                                               const int32_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col,
+                                               const double *__restrict__ val,
+                                               const double *__restrict__ rhs) {
+  constexpr int E = C * K;
+  r.pos = pos;
+  r.valid = valid;
+  r.ok = true;
+  if (!valid) {
+    r.pb = r.pe = 0;
+    return;
+  }
+  r.i = order[pos];
+  r.pb = ptr[pos];
+  r.pe = ptr[pos + 1];
+  r.acc = el_load<C, K>(rhs + size_t(r.i) * E);
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) {
+    if (r.pb + d < r.pe) {
+      r.cj[d] = col[r.pb + d];
+      load_f<C, KF, CONJ>(val + size_t(r.pb + d) * C * KF, r.f[d]);
+    }
+  }
+}
+
+// Stage 2 (one level ahead): the y values of dependencies outside the block.
+template <int C, int K, int KF, int MAXD>
+__device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const double *out,
+                                              int32_t r0, int32_t r1) {
+  constexpr int E = C * K;
+  r.ok = true;
+  if (!r.valid) return;
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) {
+    if (r.pb + d < r.pe && !(r.cj[d] >= r0 && r.cj[d] < r1)) {
+      const double *yp = out + size_t(r.cj[d]) * E;
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          double v = acc.c[c].v[k];
-          st_agent(out + size_t(i) * E + c * K + k, v != v ? __builtin_nan("") : v);
+          uint64_t bits = ld_agent(yp + c * K + k);
+          r.ok = r.ok && (bits != SENTINEL);
+          r.ye[d].c[c].v[k] = __builtin_bit_cast(double, bits);
         }
     }
   }
 }
 
-// Prepares one apply: outputs filled with SENTINEL and the two tickets
-// reset (a kernel rather than a memset, so the step can be graph-captured).
-// The abort word is reset only when abort_reset is non-null: inside a solve
-// it persists so the host sees any watchdog event at the end.
-static __global__ void trsv_prep(int64_t words, double *out1, double *out2, int32_t *ticket1,
-                          int32_t *ticket2, int32_t *abort_reset, const int32_t *done) {
+template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
+__device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int32_t *__restrict__ col,
+                                           const double *__restrict__ val,
+                                           const double *__restrict__ dval, double *out, double *lds,
+                                           int32_t r0, int32_t r1, int32_t *abort_flag) {
+  constexpr int E = C * K;
+  el<C, K> acc = r.acc;
+  {
+    const int32_t q0 = r.pb;
+    el<C, K> yv[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      if (q0 + d < r.pe) {
+        const int32_t j = r.cj[d];
+        if (j >= r0 && j < r1) {
+          yv[d] = el_load<C, K>(lds + size_t(j - r0) * E);
+        } else {
+          yv[d] = r.ye[d];
+          if (!r.ok) wait_load<C, K>(out + size_t(j) * E, yv[d], abort_flag);
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d)
+      if (q0 + d < r.pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
+  }
+  // rows with more than MAXD dependencies: remaining batches loaded here
+  for (int32_t q0 = r.pb + MAXD; q0 < r.pe; q0 += MAXD) {
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      if (q0 + d < r.pe) {
+        const int32_t j = col[q0 + d];
+        el<C, K> yj;
+        if (j >= r0 && j < r1)
+          yj = el_load<C, K>(lds + size_t(j - r0) * E);
+        else
+          wait_load<C, K>(out + size_t(j) * E, yj, abort_flag);
+        double f[C * KF];
+        load_f<C, KF, CONJ>(val + size_t(q0 + d) * C * KF, f);
+        acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, yj));
+      }
+    }
+  }
+  if constexpr (DIV) {
+    double d[C * KF];
+    load_f<C, KF, CONJ>(dval + size_t(r.pos) * C * KF, d);
+    acc = el_div_k<C, K, KF>(acc, d);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v = acc.c[c].v[k];
+      v = v != v ? __builtin_nan("") : v;
+      lds[size_t(r.i - r0) * E + c * K + k] = v;
+      st_agent(out + size_t(r.i) * E + c * K + k, v);
+    }
+}
+
+// Prefetch depth (local levels) of the blocked sweep's row data.
+template <int E> constexpr int trsv_depth() { return E <= 2 ? 4 : 2; }
+
+// About one workgroup per CU (the LDS block decides), so the register
+// budget may grow to keep the prefetch stages out of scratch.
+template <int C, int K, int KF, bool DIV, bool CONJ>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_blocked(
+    const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
+    const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
+    const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
+    const double *__restrict__ rhs, double *out, int32_t *ticket, int32_t *abort_flag,
+    const int32_t *done) {
+  if (done && *done) return;
+  extern __shared__ double lds[];
+  __shared__ int32_t cur;
+  constexpr int E = C * K;
+  constexpr int MAXD = trsv_maxd<E>() < 4 ? trsv_maxd<E>() : 4;
+  constexpr int D = trsv_depth<E>();
+  using RP = RowPre<C, K, KF, MAXD>;
+  const int32_t tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) cur = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int32_t b = cur;
+    __syncthreads();
+    if (b >= nblk) break;
+    const int32_t r0 = blk_r[2 * b], r1 = blk_r[2 * b + 1];
+    const int32_t l0 = blk_lev[b], l1 = blk_lev[b + 1];
+    RP st[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int32_t l = l0 + u;
+      if (l < l1) {
+        const int32_t pos = loc_pos[l] + tid;
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(st[u], pos, pos < loc_pos[l + 1], order, ptr, col,
+                                             val, rhs);
+      } else {
+        st[u].valid = false;
+      }
+    }
+    // external values of the first D-1 levels (their column indices are in)
+#pragma unroll
+    for (int u = 0; u + 1 < D; ++u) row_fetch_ext<C, K, KF, MAXD>(st[u], out, r0, r1);
+    // one local level: finish `now`; then request the external values of
+    // level l+D-1 (slot `ext`, whose indices arrived one stage ago) and
+    // refill `now` with the row data of level l+D
+    auto stage = [&](RP &now, RP &ext, int32_t l) {
+      const int32_t pbeg = loc_pos[l], pend = loc_pos[l + 1];
+      if (now.valid)
+        row_finish<C, K, KF, DIV, CONJ, MAXD>(now, col, val, dval, out, lds, r0, r1, abort_flag);
+      for (int32_t pos = pbeg + BLOCK + tid; pos < pend; pos += BLOCK) {
+        RP x;
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(x, pos, true, order, ptr, col, val, rhs);
+        row_fetch_ext<C, K, KF, MAXD>(x, out, r0, r1);
+        row_finish<C, K, KF, DIV, CONJ, MAXD>(x, col, val, dval, out, lds, r0, r1, abort_flag);
+      }
+      __syncthreads();
+      if (l + D - 1 < l1) row_fetch_ext<C, K, KF, MAXD>(ext, out, r0, r1);
+      if (l + D < l1) {
+        const int32_t pos = loc_pos[l + D] + tid;
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(now, pos, pos < loc_pos[l + D + 1], order, ptr, col,
+                                             val, rhs);
+      } else {
+        now.valid = false;
+      }
+    };
+    for (int32_t lv = l0; lv < l1; lv += D) {
+      if constexpr (D == 4) {
+        stage(st[0], st[3], lv);
+        if (lv + 1 < l1) stage(st[1], st[0], lv + 1);
+        if (lv + 2 < l1) stage(st[2], st[1], lv + 2);
+        if (lv + 3 < l1) stage(st[3], st[2], lv + 3);
+      } else {
+        stage(st[0], st[1], lv);
+        if (lv + 1 < l1) stage(st[1], st[0], lv + 1);
+      }
+    }
+  }
+}
+
+// Prepares one apply: outputs filled with SENTINEL, the per-level counters
+// zeroed and the two tickets reset (a kernel rather than a memset, so the
+// step can be graph-captured).  The abort word is reset only when
+// abort_reset is non-null: inside a solve it persists so the host sees any
+// watchdog event at the end.
+static __global__ void trsv_prep(int64_t words, double *out1, double *out2, int32_t nlev1,
+                                 int32_t *lev1, int32_t nlev2, int32_t *lev2, int32_t *ticket1,
+                                 int32_t *ticket2, int32_t *abort_reset, const int32_t *done) {
   if (done && *done) return;
   const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   const double sent = __builtin_bit_cast(double, (unsigned long long)SENTINEL);
@@ -287,6 +589,8 @@ static __global__ void trsv_prep(int64_t words, double *out1, double *out2, int3
     out1[i] = sent;
     out2[i] = sent;
   }
+  if (i < nlev1) lev1[i] = 0;
+  if (i < nlev2) lev2[i] = 0;
   if (i == 0) {
     *ticket1 = 0;
     *ticket2 = 0;

@@ -2,6 +2,7 @@
 // C-ABI declared in include/mpk.h.
 #include <chrono>
 #include <climits>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -60,16 +61,17 @@ size_t ilu0_layout(int64_t n, int64_t nnz, int C, int KF, int flags, Bump &b, Il
     plan_bytes(n, nnz, C, KF, false, b, &m.LH);
   }
   m.tmp = b.take<double>(size_t(n) * C * 4);
+  m.fac_order = b.take<int32_t>(size_t(n));
   return b.off;
 }
 
 template <int C, int KF>
 static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
-  const Plan &L = M.L;
-  for (int32_t l = 0; l < L.nlev; ++l) {
-    const int32_t a = L.h_levptr[l], cnt = L.h_levptr[l + 1] - a;
+  const int32_t nlev = int32_t(M.h_fac_levptr.size()) - 1;
+  for (int32_t l = 0; l < nlev; ++l) {
+    const int32_t a = M.h_fac_levptr[l], cnt = M.h_fac_levptr[l + 1] - a;
     hipLaunchKernelGGL((ilu0_level<C, KF>), dim3(nblocks(cnt)), dim3(BLOCK), 0, s, cnt,
-                       L.order + a, M.row_ptr, M.col_idx, M.diag, M.f, M.words + 1);
+                       M.fac_order + a, M.row_ptr, M.col_idx, M.diag, M.f, M.words + 1);
   }
   MPK_HIP(hipGetLastError());
   return MPK_OK;
@@ -116,12 +118,16 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   std::vector<int32_t> diag;
   host_diag(h, diag);
   HostPlan hp[4];
-  build_plan(h, diag, 0, hp[0]);
-  build_plan(h, diag, 1, hp[1]);
+  const int br = default_block_rows(C);
+  build_plan(h, diag, 0, br, hp[0]);
+  build_plan(h, diag, 1, br, hp[1]);
   if (flags & MPK_ILU0_ADJOINT) {
-    build_plan(h, diag, 2, hp[2]);
-    build_plan(h, diag, 3, hp[3]);
+    build_plan(h, diag, 2, br, hp[2]);
+    build_plan(h, diag, 3, br, hp[3]);
   }
+  M->h_fac_levptr = hp[0].glob_levptr;
+  MPK_HIP(hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
+                         hipMemcpyHostToDevice, s));
   MPK_HIP(hipMemcpyAsync(M->diag, diag.data(), sizeof(int32_t) * A->n, hipMemcpyHostToDevice, s));
   if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
   M->U.div = true;
@@ -158,10 +164,30 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
 template <int C, int K, int KF, bool DIV, bool CONJ>
 static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *abort_flag,
                         const int32_t *done, hipStream_t s) {
-  const unsigned grid = unsigned(std::min<int64_t>((P.nseg + 3) / 4, 2048));
+  if (P.mode == 1) {
+    static const int64_t bcap = [] {
+      const char *e = getenv("MPK_TRSV_BGRID");
+      return e ? std::max<int64_t>(1, atoll(e)) : int64_t(512);
+    }();
+    const unsigned grid = unsigned(std::min<int64_t>(P.nblk, bcap));
+    const size_t lds = size_t(P.blk_rows) * C * K * sizeof(double);
+    hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK),
+                       lds, s, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
+                       P.loc_pos, P.nblk, rhs, out, P.sync, abort_flag, done);
+    return;
+  }
+  static const int64_t cap = [] {
+    const char *e = getenv("MPK_TRSV_GRID");
+    return e ? std::max<int64_t>(1, atoll(e)) : int64_t(512);
+  }();
+  static const int32_t xcd = [] {
+    const char *e = getenv("MPK_TRSV_XCD");
+    return e ? std::max(1, atoi(e)) : 1;
+  }();
+  const unsigned grid = unsigned(std::min<int64_t>((P.nseg + 3) / 4, cap)) * unsigned(xcd);
   hipLaunchKernelGGL((trsv_syncfree<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK), 0,
-                     s, P.order, P.ptr, P.col, P.val, P.dval, P.seg, P.nseg, rhs, out, P.sync,
-                     abort_flag, done);
+                     s, P.order, P.ptr, P.col, P.val, P.dval, P.seg, P.seg_level, P.nseg,
+                     P.lev_size, P.lev_done, rhs, out, P.sync, abort_flag, done, xcd);
 }
 
 template <int C, int K, int KF>
@@ -170,8 +196,9 @@ static int apply_ckf(const Ilu0 &M, int conj, const double *r, double *z, int32_
   const Plan &P1 = conj ? M.UH : M.L;
   const Plan &P2 = conj ? M.LH : M.U;
   const int64_t words = M.n * C * K;
-  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(words)), dim3(BLOCK), 0, s, words, M.tmp, z, P1.sync,
-                     P2.sync, abort_reset, done);
+  const int64_t cover = std::max<int64_t>(words, std::max(P1.nlev, P2.nlev));
+  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(cover)), dim3(BLOCK), 0, s, words, M.tmp, z, P1.nlev,
+                     P1.lev_done, P2.nlev, P2.lev_done, P1.sync, P2.sync, abort_reset, done);
   if (!conj) {
     launch_trsv<C, K, KF, false, false>(P1, r, M.tmp, abort_flag, done, s);
     launch_trsv<C, K, KF, true, false>(P2, M.tmp, z, abort_flag, done, s);

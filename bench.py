@@ -148,7 +148,7 @@ def main():
     s = torch.cuda.Stream()
     y = torch.empty_like(b)
     spmv_ms = time_events(lambda: mpk.csr_spmv(A, b, y, stream=s), args.reps, s)
-    M = mpk.ilu0_factor(A, KF)
+    M = mpk.ilu0_factor(A, KF, vprec=K)
     z = torch.empty_like(b)
     apply_ms = time_events(lambda: mpk.ilu0_apply(M, b, z, stream=s), args.reps, s)
     sb = spmv_bytes(p.n, p.nnz, C, K)

@@ -117,8 +117,13 @@ int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x
  * alive until mpk_ilu0_destroy) receives the factor and the level
  * schedules; *M receives a host handle pointing into it.  flags:
  * MPK_ILU0_ADJOINT also prepares the M^H solve (needed by
- * conj_trans = 1 and by BiCG).  Synchronous; info may be NULL. */
+ * conj_trans = 1 and by BiCG); MPK_ILU0_VPREC(k) declares the largest
+ * vector precision used with it.  Synchronous; info may be NULL. */
 #define MPK_ILU0_ADJOINT 1
+/* Largest vector precision (limbs, 1..4) the factor will be applied with;
+ * it sizes the on-chip blocks of the substitutions.  0 (the default) means
+ * MPK_QD.  Applying with more limbs than declared returns MPK_EUNSUPPORTED. */
+#define MPK_ILU0_VPREC(k) ((k) << 4)
 size_t mpk_ilu0_workspace_bytes(const mpk_csr *A, mpk_prec fp, int is_complex, int flags);
 int mpk_dilu0_factor(mpk_prec fp, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
                      mpk_ilu0 **M, mpk_info *info, void *stream);

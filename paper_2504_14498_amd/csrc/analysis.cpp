@@ -81,10 +81,13 @@ void host_transpose(const HostCsr &h, std::vector<int32_t> &trp, std::vector<int
 
 // Rows per block of the blocked schedule: the block's results live in LDS,
 // at most 128 KiB for quad-double (K = 4).
-int default_block_rows(int C) {
+int default_block_rows(int C, int kmax) {
   const char *e = getenv("MPK_TRSV_BLOCK_ROWS");
   if (e) return std::max(64, atoi(e));
-  return C == 1 ? 4096 : 2048;
+  // largest power of two with rows * C * kmax doubles within 128 KiB
+  int rows = 64;
+  while (int64_t(rows) * 2 * C * kmax * 8 <= 131072) rows *= 2;
+  return rows;
 }
 
 void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, int blk_rows,
@@ -242,6 +245,19 @@ fill:
       p.src[o] = dsrcv[q];
     }
   }
+  if (p.mode == 1) {
+    p.ell_nd.assign(size_t(std::max<int64_t>(n, 1)), 0);
+    p.ell_col.assign(size_t(std::max<int64_t>(n, 1)) * ELLW, 0);
+    p.ell_src.assign(size_t(std::max<int64_t>(n, 1)) * ELLW, -1);
+    for (int64_t pos = 0; pos < n; ++pos) {
+      const int32_t a = p.ptr[pos], e = p.ptr[pos + 1];
+      p.ell_nd[pos] = e - a;
+      for (int32_t d = 0; d < ELLW && a + d < e; ++d) {
+        p.ell_col[pos * ELLW + d] = p.col[a + d];
+        p.ell_src[pos * ELLW + d] = p.src[a + d];
+      }
+    }
+  }
   p.dsrc.clear();
   if (kind == 1 || kind == 2) {
     p.dsrc.resize(size_t(std::max<int64_t>(n, 1)));
@@ -266,6 +282,10 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
     p.dval = b.take<double>(size_t(n) * C * KF);
   }
   p.sync = b.take<int32_t>(64);
+  p.ell_nd = b.take<int32_t>(size_t(n));
+  p.ell_col = b.take<int32_t>(size_t(n) * ELLW);
+  p.ell_src = b.take<int32_t>(size_t(n) * ELLW);
+  p.ell_val = b.take<double>(size_t(n) * ELLW * C * KF);
   p.blk_r = b.take<int32_t>(2 * size_t(n) + 2);
   p.blk_lev = b.take<int32_t>(size_t(n) + 1);
   p.loc_pos = b.take<int32_t>(size_t(n) + 1);
@@ -296,6 +316,11 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
                            hipMemcpyHostToDevice, s));
     hb += hp.blk_lev.size();
     MPK_HIP(hipMemcpyAsync(p.loc_pos, hb, sizeof(int32_t) * hp.loc_pos.size(),
+                           hipMemcpyHostToDevice, s));
+    MPK_HIP(hipMemcpyAsync(p.ell_nd, hp.ell_nd.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    MPK_HIP(hipMemcpyAsync(p.ell_col, hp.ell_col.data(), sizeof(int32_t) * n * ELLW,
+                           hipMemcpyHostToDevice, s));
+    MPK_HIP(hipMemcpyAsync(p.ell_src, hp.ell_src.data(), sizeof(int32_t) * n * ELLW,
                            hipMemcpyHostToDevice, s));
   }
   MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));

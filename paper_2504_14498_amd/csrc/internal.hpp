@@ -15,6 +15,7 @@ constexpr int BLOCK = 256;          // threads per workgroup for row/element ker
 constexpr int WAVE = 64;            // CDNA wavefront
 constexpr int MAX_PARTIAL_BLOCKS = 8192;
 constexpr int MAXE = 8;             // max doubles per element (C * K)
+constexpr int ELLW = 4;             // flat dependency slots per row (blocked sweeps)
 
 // Bit pattern marking "not yet computed" in the outputs of the sync-free
 // triangular solves: a NaN payload that arithmetic never produces (stored
@@ -87,11 +88,19 @@ struct Plan {
   // each with its own local levels; positions are block-major
   int32_t mode = 0;            // 0 level schedule, 1 blocked schedule
   int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
+  int32_t kmax = 4;            // largest vector precision the blocks are sized for
   int32_t blk_rows = 0;        // rows per block
   int32_t *blk_r = nullptr;    // [2*nblk] row range [r0, r1) of each block
   int32_t *blk_lev = nullptr;  // [nblk+1] first local level of each block
   int32_t *loc_pos = nullptr;  // [nloc+1] first position of each local level
+  // flat per-position dependency slots (blocked schedule): up to ELLW
+  // dependencies of the row at position pos live at [pos * ELLW + d]
+  int32_t *ell_nd = nullptr;   // [n] dependencies of each position
+  int32_t *ell_col = nullptr;  // [n * ELLW]
+  int32_t *ell_src = nullptr;  // [n * ELLW] value source in A's pattern (-1 pad)
+  double *ell_val = nullptr;   // [n * ELLW * C * KF]
   std::vector<int32_t> h_blk;  // host copies kept alive for the uploads
+  std::vector<int32_t> h_ell;
   std::vector<int32_t> h_levptr;   // level boundaries (host)
   std::vector<int32_t> h_levsize;  // level sizes (host copy kept alive for the upload)
   bool div = false, conj = false;
@@ -161,7 +170,7 @@ struct HostPlan {
   std::vector<int32_t> order, ptr, col, src, dsrc, seg, seg_level, levptr;
   int32_t nlev = 0;
   int32_t mode = 0, nblk = 0, blk_rows = 0;
-  std::vector<int32_t> blk_r, blk_lev, loc_pos;
+  std::vector<int32_t> blk_r, blk_lev, loc_pos, ell_nd, ell_col, ell_src;
   std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)
 };
 // kind: 0 = L (strict lower of rows, forward), 1 = U (strict upper, backward,
@@ -169,7 +178,7 @@ struct HostPlan {
 // 3 = L^H (columns of the strict lower part, backward).
 void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, int blk_rows,
                 HostPlan &p);
-int default_block_rows(int C);
+int default_block_rows(int C, int kmax);
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out);
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);
 

@@ -110,6 +110,10 @@ static __global__ void gather_vals(int64_t m, int C, int KF, const int32_t *__re
   const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   if (i >= m) return;
   const int V = C * KF;
+  if (src[i] < 0) {
+    for (int v = 0; v < V; ++v) to[size_t(i) * V + v] = 0.0;
+    return;
+  }
   const double *s = from + size_t(src[i]) * V;
   for (int v = 0; v < V; ++v) to[size_t(i) * V + v] = (conj && v >= KF) ? -s[v] : s[v];
 }
@@ -382,15 +386,15 @@ template <int C, int K, int KF, int MAXD> struct RowPre {
   bool ok;
 };
 
-// Stage 1 (several levels ahead): the row's own data and factor values.
+// Stage 1 (several levels ahead): the row index, its dependency count,
+// the first ELLW dependency columns and their factor values -- all indexed
+// by the position, so one memory round trip covers the stage.
 template <int C, int K, int KF, bool CONJ, int MAXD>
 __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_t pos, bool valid,
                                                const int32_t *__restrict__ order,
-                                               const int32_t *__restrict__ ptr,
-                                               const int32_t *__restrict__ col,
-                                               const double *__restrict__ val,
-                                               const double *__restrict__ rhs) {
-  constexpr int E = C * K;
+                                               const int32_t *__restrict__ ell_nd,
+                                               const int32_t *__restrict__ ell_col,
+                                               const double *__restrict__ ell_val) {
   r.pos = pos;
   r.valid = valid;
   r.ok = true;
@@ -399,15 +403,12 @@ __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_
     return;
   }
   r.i = order[pos];
-  r.pb = ptr[pos];
-  r.pe = ptr[pos + 1];
-  r.acc = el_load<C, K>(rhs + size_t(r.i) * E);
+  r.pb = 0;
+  r.pe = ell_nd[pos];
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
-    if (r.pb + d < r.pe) {
-      r.cj[d] = col[r.pb + d];
-      load_f<C, KF, CONJ>(val + size_t(r.pb + d) * C * KF, r.f[d]);
-    }
+    r.cj[d] = ell_col[size_t(pos) * ELLW + d];
+    load_f<C, KF, CONJ>(ell_val + (size_t(pos) * ELLW + d) * C * KF, r.f[d]);
   }
 }
 
@@ -420,7 +421,7 @@ __device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const d
   if (!r.valid) return;
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
-    if (r.pb + d < r.pe && !(r.cj[d] >= r0 && r.cj[d] < r1)) {
+    if (d < r.pe && !(r.cj[d] >= r0 && r.cj[d] < r1)) {
       const double *yp = out + size_t(r.cj[d]) * E;
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -435,18 +436,20 @@ __device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const d
 }
 
 template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
-__device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int32_t *__restrict__ col,
+__device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int32_t *__restrict__ ptr,
+                                           const int32_t *__restrict__ col,
                                            const double *__restrict__ val,
                                            const double *__restrict__ dval, double *out, double *lds,
                                            int32_t r0, int32_t r1, int32_t *abort_flag) {
   constexpr int E = C * K;
-  el<C, K> acc = r.acc;
+  // the block's rhs was staged into LDS; the slot of row i holds rhs_i until
+  // y_i replaces it
+  el<C, K> acc = el_load<C, K>(lds + size_t(r.i - r0) * E);
   {
-    const int32_t q0 = r.pb;
     el<C, K> yv[MAXD];
 #pragma unroll
     for (int d = 0; d < MAXD; ++d) {
-      if (q0 + d < r.pe) {
+      if (d < r.pe) {
         const int32_t j = r.cj[d];
         if (j >= r0 && j < r1) {
           yv[d] = el_load<C, K>(lds + size_t(j - r0) * E);
@@ -458,23 +461,21 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
     }
 #pragma unroll
     for (int d = 0; d < MAXD; ++d)
-      if (q0 + d < r.pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
+      if (d < r.pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
   }
-  // rows with more than MAXD dependencies: remaining batches loaded here
-  for (int32_t q0 = r.pb + MAXD; q0 < r.pe; q0 += MAXD) {
-#pragma unroll
-    for (int d = 0; d < MAXD; ++d) {
-      if (q0 + d < r.pe) {
-        const int32_t j = col[q0 + d];
-        el<C, K> yj;
-        if (j >= r0 && j < r1)
-          yj = el_load<C, K>(lds + size_t(j - r0) * E);
-        else
-          wait_load<C, K>(out + size_t(j) * E, yj, abort_flag);
-        double f[C * KF];
-        load_f<C, KF, CONJ>(val + size_t(q0 + d) * C * KF, f);
-        acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, yj));
-      }
+  // rows with more than MAXD dependencies: the rest from the CSR arrays
+  if (r.pe > MAXD) {
+    const int32_t pb = ptr[r.pos];
+    for (int32_t d = MAXD; d < r.pe; ++d) {
+      const int32_t j = col[pb + d];
+      el<C, K> yj;
+      if (j >= r0 && j < r1)
+        yj = el_load<C, K>(lds + size_t(j - r0) * E);
+      else
+        wait_load<C, K>(out + size_t(j) * E, yj, abort_flag);
+      double f[C * KF];
+      load_f<C, KF, CONJ>(val + size_t(pb + d) * C * KF, f);
+      acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, yj));
     }
   }
   if constexpr (DIV) {
@@ -493,6 +494,15 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
     }
 }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations, not for its outstanding global loads and stores
+// (a full __syncthreads would drain the prefetch pipeline at every level).
+// The asm statement also keeps the compiler from moving memory accesses
+// across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Prefetch depth (local levels) of the blocked sweep's row data.
 template <int E> constexpr int trsv_depth() { return E <= 2 ? 4 : 2; }
 
@@ -504,13 +514,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
     const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
-    const double *__restrict__ rhs, double *out, int32_t *ticket, int32_t *abort_flag,
-    const int32_t *done) {
+    const int32_t *__restrict__ ell_nd, const int32_t *__restrict__ ell_col,
+    const double *__restrict__ ell_val, const double *__restrict__ rhs, double *out,
+    int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
   if (done && *done) return;
   extern __shared__ double lds[];
   __shared__ int32_t cur;
   constexpr int E = C * K;
-  constexpr int MAXD = trsv_maxd<E>() < 4 ? trsv_maxd<E>() : 4;
+  constexpr int MAXD = ELLW;
   constexpr int D = trsv_depth<E>();
   using RP = RowPre<C, K, KF, MAXD>;
   const int32_t tid = threadIdx.x;
@@ -522,18 +533,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     if (b >= nblk) break;
     const int32_t r0 = blk_r[2 * b], r1 = blk_r[2 * b + 1];
     const int32_t l0 = blk_lev[b], l1 = blk_lev[b + 1];
+    // stage the block's right-hand side into LDS (contiguous rows)
+    for (int64_t w = tid; w < int64_t(r1 - r0) * E; w += BLOCK) lds[w] = rhs[size_t(r0) * E + w];
     RP st[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) {
       const int32_t l = l0 + u;
       if (l < l1) {
         const int32_t pos = loc_pos[l] + tid;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(st[u], pos, pos < loc_pos[l + 1], order, ptr, col,
-                                             val, rhs);
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(st[u], pos, pos < loc_pos[l + 1], order, ell_nd,
+                                             ell_col, ell_val);
       } else {
         st[u].valid = false;
       }
     }
+    __syncthreads();
     // external values of the first D-1 levels (their column indices are in)
 #pragma unroll
     for (int u = 0; u + 1 < D; ++u) row_fetch_ext<C, K, KF, MAXD>(st[u], out, r0, r1);
@@ -543,19 +557,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     auto stage = [&](RP &now, RP &ext, int32_t l) {
       const int32_t pbeg = loc_pos[l], pend = loc_pos[l + 1];
       if (now.valid)
-        row_finish<C, K, KF, DIV, CONJ, MAXD>(now, col, val, dval, out, lds, r0, r1, abort_flag);
+        row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, dval, out, lds, r0, r1,
+                                              abort_flag);
       for (int32_t pos = pbeg + BLOCK + tid; pos < pend; pos += BLOCK) {
         RP x;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(x, pos, true, order, ptr, col, val, rhs);
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(x, pos, true, order, ell_nd, ell_col, ell_val);
         row_fetch_ext<C, K, KF, MAXD>(x, out, r0, r1);
-        row_finish<C, K, KF, DIV, CONJ, MAXD>(x, col, val, dval, out, lds, r0, r1, abort_flag);
+        row_finish<C, K, KF, DIV, CONJ, MAXD>(x, ptr, col, val, dval, out, lds, r0, r1,
+                                              abort_flag);
       }
-      __syncthreads();
+      lds_barrier();
       if (l + D - 1 < l1) row_fetch_ext<C, K, KF, MAXD>(ext, out, r0, r1);
       if (l + D < l1) {
         const int32_t pos = loc_pos[l + D] + tid;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(now, pos, pos < loc_pos[l + D + 1], order, ptr, col,
-                                             val, rhs);
+        row_fetch_meta<C, K, KF, CONJ, MAXD>(now, pos, pos < loc_pos[l + D + 1], order, ell_nd,
+                                             ell_col, ell_val);
       } else {
         now.valid = false;
       }

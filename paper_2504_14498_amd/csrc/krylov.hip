@@ -751,7 +751,8 @@ static int krylov_run(int method, int KF, double tol_rel, double tol_abs, int64_
     // the ILU(0) part of the workspace starts at its first array; carving it
     // again from there reproduces the same offsets
     const size_t used = size_t(reinterpret_cast<char *>(S.L.ilu.words) - static_cast<char *>(ws));
-    st = ilu0_factor_impl(C, KF, A, method == MPK_BICG ? MPK_ILU0_ADJOINT : 0,
+    st = ilu0_factor_impl(C, KF, A,
+                          (method == MPK_BICG ? MPK_ILU0_ADJOINT : 0) | MPK_ILU0_VPREC(K),
                           static_cast<void *>(S.L.ilu.words), ws_bytes - used, &S.L.ilu, &finfo, s);
     if (st) {
       if (info) info->bad_row = finfo.bad_row;

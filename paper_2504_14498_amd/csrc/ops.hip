@@ -2,6 +2,7 @@
 // C-ABI declared in include/mpk.h.
 #include <chrono>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -78,6 +79,9 @@ static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
 }
 
 static int gather_plan(const Plan &P, const Ilu0 &M, hipStream_t s) {
+  if (P.mode == 1 && P.n > 0)
+    hipLaunchKernelGGL(gather_vals, dim3(nblocks(P.n * ELLW)), dim3(BLOCK), 0, s, P.n * ELLW, M.C,
+                       M.KF, P.ell_src, M.f, P.ell_val, 0);
   if (P.nnz > 0)
     hipLaunchKernelGGL(gather_vals, dim3(nblocks(P.nnz)), dim3(BLOCK), 0, s, P.nnz, M.C, M.KF,
                        P.src, M.f, P.val, 0);
@@ -88,9 +92,24 @@ static int gather_plan(const Plan &P, const Ilu0 &M, hipStream_t s) {
   return MPK_OK;
 }
 
+static bool timing_on() {
+  static const bool on = getenv("MPK_TIMING") != nullptr;
+  return on;
+}
+#define MPK_PHASE(name)                                                          \
+  do {                                                                           \
+    if (timing_on()) {                                                           \
+      hipStreamSynchronize(s);                                                   \
+      const double t_ = now_ms();                                                \
+      fprintf(stderr, "[mpk] %-22s %8.2f ms\n", name, t_ - tp);                  \
+      tp = t_;                                                                   \
+    }                                                                            \
+  } while (0)
+
 int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
                      Ilu0 *M, mpk_info *info, hipStream_t s) {
   const double t0 = now_ms();
+  double tp = t0;
   int64_t bad = -1;
   if (info) info->bad_row = -1;
   Bump b(ws);
@@ -105,6 +124,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   HostCsr h;
   int st = fetch_pattern(A, h, s);
   if (st) return st;
+  MPK_PHASE("fetch pattern");
   st = check_pattern(h, &bad);
   if (st) {
     if (info) info->bad_row = bad;
@@ -115,16 +135,19 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     if (info) info->bad_row = bad;
     return st;
   }
+  MPK_PHASE("check pattern+values");
   std::vector<int32_t> diag;
   host_diag(h, diag);
   HostPlan hp[4];
-  const int br = default_block_rows(C);
+  const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
+  const int br = default_block_rows(C, kmax);
   build_plan(h, diag, 0, br, hp[0]);
   build_plan(h, diag, 1, br, hp[1]);
   if (flags & MPK_ILU0_ADJOINT) {
     build_plan(h, diag, 2, br, hp[2]);
     build_plan(h, diag, 3, br, hp[3]);
   }
+  MPK_PHASE("build plans (host)");
   M->h_fac_levptr = hp[0].glob_levptr;
   MPK_HIP(hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
                          hipMemcpyHostToDevice, s));
@@ -132,12 +155,14 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
   M->U.div = true;
   M->L.div = false;
+  M->L.kmax = M->U.kmax = M->UH.kmax = M->LH.kmax = kmax;
   if (flags & MPK_ILU0_ADJOINT) {
     if ((st = upload_plan(hp[2], M->UH, s)) || (st = upload_plan(hp[3], M->LH, s))) return st;
     M->UH.div = true;
     M->LH.div = false;
     M->UH.conj = M->LH.conj = true;
   }
+  MPK_PHASE("upload plans");
   int32_t init[3] = {0, INT_MAX, INT_MAX};
   MPK_HIP(hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(promote_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, KF, A->val,
@@ -146,6 +171,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   st = (C == 1 ? (KF == 1 ? ilu0_levels<1, 1>(*M, s) : ilu0_levels<1, 2>(*M, s))
                : (KF == 1 ? ilu0_levels<2, 1>(*M, s) : ilu0_levels<2, 2>(*M, s)));
   if (st) return st;
+  MPK_PHASE("factor levels");
   int32_t badpiv = INT_MAX;
   MPK_HIP(hipMemcpyAsync(&badpiv, M->words + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MPK_HIP(hipStreamSynchronize(s));
@@ -157,6 +183,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   if (flags & MPK_ILU0_ADJOINT)
     if ((st = gather_plan(M->UH, *M, s)) || (st = gather_plan(M->LH, *M, s))) return st;
   MPK_HIP(hipStreamSynchronize(s));
+  MPK_PHASE("gather values");
   if (info) info->setup_ms = now_ms() - t0;
   return MPK_OK;
 }
@@ -173,7 +200,8 @@ static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
     const size_t lds = size_t(P.blk_rows) * C * K * sizeof(double);
     hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK),
                        lds, s, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
-                       P.loc_pos, P.nblk, rhs, out, P.sync, abort_flag, done);
+                       P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_val, rhs, out, P.sync,
+                       abort_flag, done);
     return;
   }
   static const int64_t cap = [] {
@@ -213,6 +241,7 @@ int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z
                       int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
                       hipStream_t s) {
   if (K < M.KF || K < 1 || K > 4) return MPK_EUNSUPPORTED;
+  if (K > M.L.kmax) return MPK_EUNSUPPORTED;
   if (conj && !(M.flags & MPK_ILU0_ADJOINT)) return MPK_EUNSUPPORTED;
   return dispatch_ck(M.C, K, [&]<int C, int KK>() {
     if constexpr (KK >= 2) {
@@ -326,7 +355,9 @@ static int ilu0_factor(int C, mpk_prec fp, const mpk_csr *A, int flags, void *ws
                        mpk_ilu0 **M, mpk_info *info, void *stream) {
   int st = validate_csr_args(A);
   if (st) return st;
-  if ((fp != MPK_D && fp != MPK_DD) || !M || (flags & ~MPK_ILU0_ADJOINT)) return MPK_EINVAL;
+  if ((fp != MPK_D && fp != MPK_DD) || !M || (flags & ~(MPK_ILU0_ADJOINT | (7 << 4))) ||
+      ((flags >> 4) & 7) > 4 || (((flags >> 4) & 7) && ((flags >> 4) & 7) < int(fp)))
+    return MPK_EINVAL;
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
       ws_bytes < mpk_ilu0_workspace_bytes(A, fp, C == 2, flags))
     return MPK_EWORKSPACE;

@@ -175,9 +175,13 @@ class Ilu0:
             self.handle = None
 
 
-def ilu0_factor(A, fprec=1, adjoint=False, stream=None):
-    """ILU(0) factorisation in binary64 (fprec=1) or double-double (2)."""
+def ilu0_factor(A, fprec=1, adjoint=False, vprec=None, stream=None):
+    """ILU(0) factorisation in binary64 (fprec=1) or double-double (2).
+    vprec: largest vector precision the factor will be applied with (sizes
+    the on-chip blocks of the substitutions; default 4 = QD)."""
     flags = ILU0_ADJOINT if adjoint else 0
+    if vprec is not None:
+        flags |= int(vprec) << 4
     nb = _lib().mpk_ilu0_workspace_bytes(ctypes.byref(A.c), fprec, int(A.is_complex), flags)
     if nb == 0:
         raise ValueError("bad ILU(0) arguments")

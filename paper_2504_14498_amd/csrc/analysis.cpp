@@ -90,179 +90,109 @@ int default_block_rows(int C, int kmax) {
   return rows;
 }
 
-void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, int blk_rows,
-                HostPlan &p) {
-  const int64_t n = h.n;
-  // dependency lists per row: (column, source position), ascending column
-  std::vector<int32_t> dptr(size_t(n) + 1, 0), dcol, dsrcv;
-  if (kind == 0 || kind == 1) {
-    for (int64_t i = 0; i < n; ++i) {
-      int cnt = 0;
-      for (int32_t q = h.rp[i]; q < h.rp[i + 1]; ++q)
-        if (kind == 0 ? h.ci[q] < i : h.ci[q] > i) ++cnt;
-      dptr[i + 1] = dptr[i] + cnt;
-    }
-    dcol.resize(size_t(dptr[n]) + 1);
-    dsrcv.resize(size_t(dptr[n]) + 1);
-    for (int64_t i = 0; i < n; ++i) {
-      int32_t o = dptr[i];
-      for (int32_t q = h.rp[i]; q < h.rp[i + 1]; ++q)
-        if (kind == 0 ? h.ci[q] < i : h.ci[q] > i) {
-          dcol[o] = h.ci[q];
-          dsrcv[o] = q;
-          ++o;
-        }
-    }
-  } else {
-    std::vector<int32_t> trp, tci, tsrc;
-    host_transpose(h, trp, tci, tsrc);
-    for (int64_t i = 0; i < n; ++i) {
-      int cnt = 0;
-      for (int32_t q = trp[i]; q < trp[i + 1]; ++q)
-        if (kind == 2 ? tci[q] < i : tci[q] > i) ++cnt;
-      dptr[i + 1] = dptr[i] + cnt;
-    }
-    dcol.resize(size_t(dptr[n]) + 1);
-    dsrcv.resize(size_t(dptr[n]) + 1);
-    for (int64_t i = 0; i < n; ++i) {
-      int32_t o = dptr[i];
-      for (int32_t q = trp[i]; q < trp[i + 1]; ++q)
-        if (kind == 2 ? tci[q] < i : tci[q] > i) {
-          dcol[o] = tci[q];
-          dsrcv[o] = tsrc[q];
-          ++o;
-        }
+// Dependency lists of the four sweeps, read straight from a CSR (rows of
+// A for L and U, rows of A^T for U^H and L^H): row i depends on the stored
+// columns j < i (forward kinds 0, 2) or j > i (backward kinds 1, 3).
+struct DepView {
+  const int32_t *rp, *ci;
+  bool lower;
+  // rows are sorted: the lower part is a prefix, the upper part a suffix
+  template <class F> void each(int64_t i, F &&f) const {
+    if (lower) {
+      for (int32_t q = rp[i]; q < rp[i + 1] && ci[q] < i; ++q) f(ci[q]);
+    } else {
+      for (int32_t q = rp[i + 1] - 1; q >= rp[i] && ci[q] > i; --q) f(ci[q]);
     }
   }
+};
+
+void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
+  const int64_t n = h.n;
+  const HostCsr &g = (kind >= 2) ? *ht : h;
+  const DepView dv{g.rp.data(), g.ci.data(), kind == 0 || kind == 2};
   const bool forward = (kind == 0 || kind == 2);
+  int shift = 0;
+  while ((int64_t(1) << shift) < blk_rows) ++shift;
+  // global levels (the level schedule and the factorisation need them), and
+  // the share of block-internal dependencies that picks the schedule
   std::vector<int32_t> lvl(size_t(n), 0);
   int32_t nlev = n > 0 ? 1 : 0;
+  int64_t internal = 0, total = 0;
   for (int64_t t = 0; t < n; ++t) {
-    int64_t i = forward ? t : n - 1 - t;
+    const int64_t i = forward ? t : n - 1 - t;
+    const int64_t bi = i >> shift;
     int32_t l = 0;
-    for (int32_t q = dptr[i]; q < dptr[i + 1]; ++q) l = std::max(l, lvl[dcol[q]] + 1);
+    dv.each(i, [&](int32_t j) {
+      l = std::max(l, lvl[j] + 1);
+      ++total;
+      internal += (int64_t(j) >> shift) == bi;
+    });
     lvl[i] = l;
     nlev = std::max(nlev, l + 1);
   }
-  // blocked schedule: blocks of blk_rows consecutive rows, taken in the
-  // sweep's direction; used when most dependencies stay inside a block
-  p.mode = 0;
-  {
-    int64_t internal = 0, total = dptr[n];
-    for (int64_t i = 0; i < n; ++i)
-      for (int32_t q = dptr[i]; q < dptr[i + 1]; ++q)
-        internal += (dcol[q] / blk_rows) == (i / blk_rows);
-    const char *e = getenv("MPK_TRSV_MODE");
-    if (e && e[0] == 'b')
-      p.mode = 1;
-    else if (e && e[0] == 'l')
-      p.mode = 0;
-    else
-      p.mode = (total > 0 && 2 * internal >= total) ? 1 : 0;
-  }
-  if (kind == 0) {
-    // the factorisation walks the global forward levels
-    p.glob_levptr.assign(size_t(nlev) + 1, 0);
-    for (int64_t i = 0; i < n; ++i) p.glob_levptr[lvl[i] + 1]++;
-    for (int32_t l = 0; l < nlev; ++l) p.glob_levptr[l + 1] += p.glob_levptr[l];
-    p.glob_order.resize(size_t(std::max<int64_t>(n, 1)));
-    std::vector<int32_t> next(p.glob_levptr.begin(), p.glob_levptr.end() - 1);
-    for (int64_t i = 0; i < n; ++i) p.glob_order[next[lvl[i]]++] = int32_t(i);
-  }
-  if (p.mode == 1) {
-    p.blk_rows = blk_rows;
-    p.nblk = int32_t((n + blk_rows - 1) / blk_rows);
-    p.blk_r.assign(size_t(2) * p.nblk, 0);
-    p.blk_lev.assign(size_t(p.nblk) + 1, 0);
-    p.loc_pos.clear();
-    p.order.clear();
-    std::vector<int32_t> loc(size_t(blk_rows), 0);
-    for (int32_t b = 0; b < p.nblk; ++b) {
-      // processing order: ascending blocks forward, descending backward
-      const int32_t nb = forward ? b : p.nblk - 1 - b;
-      const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
-      p.blk_r[2 * b] = int32_t(r0);
-      p.blk_r[2 * b + 1] = int32_t(r1);
-      int32_t nl = 1;
-      for (int64_t t = 0; t < r1 - r0; ++t) {
-        const int64_t i = forward ? r0 + t : r1 - 1 - t;
-        int32_t l = 0;
-        for (int32_t q = dptr[i]; q < dptr[i + 1]; ++q) {
-          const int32_t j = dcol[q];
-          if (j >= r0 && j < r1) l = std::max(l, loc[j - r0] + 1);
-        }
-        loc[i - r0] = l;
-        nl = std::max(nl, l + 1);
-      }
-      p.blk_lev[b] = int32_t(p.loc_pos.size());
-      std::vector<int32_t> cnt(size_t(nl) + 1, 0);
-      for (int64_t i = r0; i < r1; ++i) cnt[loc[i - r0] + 1]++;
-      for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
-      const int32_t base = int32_t(p.order.size());
-      for (int32_t l = 0; l < nl; ++l) p.loc_pos.push_back(base + cnt[l]);
-      p.order.resize(size_t(base) + size_t(r1 - r0));
-      for (int64_t i = r0; i < r1; ++i) p.order[base + cnt[loc[i - r0]]++] = int32_t(i);
-    }
-    p.blk_lev[p.nblk] = int32_t(p.loc_pos.size());
-    p.loc_pos.push_back(int32_t(n));
-    p.nlev = nlev;
-    p.levptr.assign(2, 0);
-    p.levptr[1] = int32_t(n);
-    p.seg.assign(1, int32_t(n));
-    p.seg_level.assign(1, 0);
-    goto fill;
-  }
+  p.mode = (total > 0 && 2 * internal >= total) ? 1 : 0;
+  if (const char *e = getenv("MPK_TRSV_MODE")) p.mode = (e[0] == 'b') ? 1 : (e[0] == 'l' ? 0 : p.mode);
   p.nlev = nlev;
-  p.levptr.assign(size_t(nlev) + 1, 0);
-  for (int64_t i = 0; i < n; ++i) p.levptr[lvl[i] + 1]++;
-  for (int32_t l = 0; l < nlev; ++l) p.levptr[l + 1] += p.levptr[l];
-  p.order.resize(size_t(std::max<int64_t>(n, 1)));
-  {
-    std::vector<int32_t> next(p.levptr.begin(), p.levptr.end() - 1);
-    for (int64_t i = 0; i < n; ++i) p.order[next[lvl[i]]++] = int32_t(i);
-  }
-  p.seg.clear();
-  p.seg_level.clear();
-  for (int32_t l = 0; l < nlev; ++l)
-    for (int32_t s = p.levptr[l]; s < p.levptr[l + 1]; s += WAVE) {
-      p.seg.push_back(s);
-      p.seg_level.push_back(l);
-    }
-  p.seg.push_back(int32_t(n));
-fill:
-  p.ptr.assign(size_t(n) + 1, 0);
-  for (int64_t pos = 0; pos < n; ++pos) {
-    int32_t i = p.order[pos];
-    p.ptr[pos + 1] = p.ptr[pos] + (dptr[i + 1] - dptr[i]);
-  }
-  p.col.resize(size_t(p.ptr[n]) + 1);
-  p.src.resize(size_t(p.ptr[n]) + 1);
-  for (int64_t pos = 0; pos < n; ++pos) {
-    int32_t i = p.order[pos];
-    int32_t o = p.ptr[pos];
-    for (int32_t q = dptr[i]; q < dptr[i + 1]; ++q, ++o) {
-      p.col[o] = dcol[q];
-      p.src[o] = dsrcv[q];
-    }
-  }
-  if (p.mode == 1) {
-    p.ell_nd.assign(size_t(std::max<int64_t>(n, 1)), 0);
-    p.ell_col.assign(size_t(std::max<int64_t>(n, 1)) * ELLW, 0);
-    p.ell_src.assign(size_t(std::max<int64_t>(n, 1)) * ELLW, -1);
-    for (int64_t pos = 0; pos < n; ++pos) {
-      const int32_t a = p.ptr[pos], e = p.ptr[pos + 1];
-      p.ell_nd[pos] = e - a;
-      for (int32_t d = 0; d < ELLW && a + d < e; ++d) {
-        p.ell_col[pos * ELLW + d] = p.col[a + d];
-        p.ell_src[pos * ELLW + d] = p.src[a + d];
+  auto counting_order = [&](std::vector<int32_t> &levptr, std::vector<int32_t> &order) {
+    levptr.assign(size_t(nlev) + 1, 0);
+    for (int64_t i = 0; i < n; ++i) levptr[lvl[i] + 1]++;
+    for (int32_t l = 0; l < nlev; ++l) levptr[l + 1] += levptr[l];
+    order.resize(size_t(std::max<int64_t>(n, 1)));
+    std::vector<int32_t> next(levptr.begin(), levptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) order[next[lvl[i]]++] = int32_t(i);
+  };
+  if (kind == 0) counting_order(p.glob_levptr, p.glob_order);
+  if (p.mode == 0) {
+    counting_order(p.levptr, p.order);
+    p.seg.clear();
+    p.seg_level.clear();
+    for (int32_t l = 0; l < nlev; ++l)
+      for (int32_t s = p.levptr[l]; s < p.levptr[l + 1]; s += WAVE) {
+        p.seg.push_back(s);
+        p.seg_level.push_back(l);
       }
+    p.seg.push_back(int32_t(n));
+    return;
+  }
+  // blocked schedule: blocks of blk_rows consecutive rows taken in the
+  // sweep's direction, each ordered by its local (block-internal) levels
+  p.blk_rows = blk_rows;
+  p.nblk = int32_t((n + blk_rows - 1) / blk_rows);
+  p.blk_r.assign(size_t(2) * p.nblk, 0);
+  p.blk_lev.assign(size_t(p.nblk) + 1, 0);
+  p.loc_pos.clear();
+  p.order.assign(size_t(std::max<int64_t>(n, 1)), 0);
+  std::vector<int32_t> loc(size_t(blk_rows), 0), cnt;
+  int32_t base = 0;
+  for (int32_t b = 0; b < p.nblk; ++b) {
+    const int32_t nb = forward ? b : p.nblk - 1 - b;
+    const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
+    p.blk_r[2 * b] = int32_t(r0);
+    p.blk_r[2 * b + 1] = int32_t(r1);
+    int32_t nl = 1;
+    for (int64_t t = 0; t < r1 - r0; ++t) {
+      const int64_t i = forward ? r0 + t : r1 - 1 - t;
+      int32_t l = 0;
+      dv.each(i, [&](int32_t j) {
+        if (j >= r0 && j < r1) l = std::max(l, loc[j - r0] + 1);
+      });
+      loc[i - r0] = l;
+      nl = std::max(nl, l + 1);
     }
+    p.blk_lev[b] = int32_t(p.loc_pos.size());
+    cnt.assign(size_t(nl) + 1, 0);
+    for (int64_t i = r0; i < r1; ++i) cnt[loc[i - r0] + 1]++;
+    for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
+    for (int32_t l = 0; l < nl; ++l) p.loc_pos.push_back(base + cnt[l]);
+    for (int64_t i = r0; i < r1; ++i) p.order[base + cnt[loc[i - r0]]++] = int32_t(i);
+    base += int32_t(r1 - r0);
   }
-  p.dsrc.clear();
-  if (kind == 1 || kind == 2) {
-    p.dsrc.resize(size_t(std::max<int64_t>(n, 1)));
-    for (int64_t pos = 0; pos < n; ++pos) p.dsrc[pos] = diag[p.order[pos]];
-  }
+  p.blk_lev[p.nblk] = int32_t(p.loc_pos.size());
+  p.loc_pos.push_back(int32_t(n));
+  p.levptr.assign(2, 0);
+  p.levptr[1] = int32_t(n);
+  p.seg.assign(1, int32_t(n));
+  p.seg_level.assign(1, 0);
 }
 
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out) {
@@ -294,15 +224,15 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
 }
 
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
-  const int64_t n = int64_t(hp.ptr.size()) - 1;
-  p.n = n;
-  p.nnz = hp.ptr[n];
+  const int64_t n = int64_t(hp.order.size()) > 0 ? int64_t(hp.order.size()) : 0;
   p.nlev = hp.nlev;
   p.nseg = int32_t(hp.seg.size()) - 1;
   p.h_levptr = hp.levptr;
   p.mode = hp.mode;
   p.nblk = hp.nblk;
   p.blk_rows = hp.blk_rows;
+  MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * p.n, hipMemcpyHostToDevice, s));
+  (void)n;
   if (hp.mode == 1) {
     p.nloc = int32_t(hp.loc_pos.size()) - 1;
     p.h_blk.clear();
@@ -317,31 +247,17 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
     hb += hp.blk_lev.size();
     MPK_HIP(hipMemcpyAsync(p.loc_pos, hb, sizeof(int32_t) * hp.loc_pos.size(),
                            hipMemcpyHostToDevice, s));
-    MPK_HIP(hipMemcpyAsync(p.ell_nd, hp.ell_nd.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-    MPK_HIP(hipMemcpyAsync(p.ell_col, hp.ell_col.data(), sizeof(int32_t) * n * ELLW,
+  } else {
+    MPK_HIP(hipMemcpyAsync(p.seg, hp.seg.data(), sizeof(int32_t) * hp.seg.size(),
                            hipMemcpyHostToDevice, s));
-    MPK_HIP(hipMemcpyAsync(p.ell_src, hp.ell_src.data(), sizeof(int32_t) * n * ELLW,
-                           hipMemcpyHostToDevice, s));
-  }
-  MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  MPK_HIP(hipMemcpyAsync(p.ptr, hp.ptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
-  if (p.nnz > 0) {
-    MPK_HIP(hipMemcpyAsync(p.col, hp.col.data(), sizeof(int32_t) * p.nnz, hipMemcpyHostToDevice, s));
-    MPK_HIP(hipMemcpyAsync(p.src, hp.src.data(), sizeof(int32_t) * p.nnz, hipMemcpyHostToDevice, s));
-  }
-  MPK_HIP(hipMemcpyAsync(p.seg, hp.seg.data(), sizeof(int32_t) * hp.seg.size(),
-                         hipMemcpyHostToDevice, s));
-  MPK_HIP(hipMemcpyAsync(p.seg_level, hp.seg_level.data(), sizeof(int32_t) * hp.seg_level.size(),
-                         hipMemcpyHostToDevice, s));
-  {
+    MPK_HIP(hipMemcpyAsync(p.seg_level, hp.seg_level.data(),
+                           sizeof(int32_t) * hp.seg_level.size(), hipMemcpyHostToDevice, s));
     std::vector<int32_t> sz(size_t(hp.nlev) + 1, 0);
     for (int32_t l = 0; l < hp.nlev; ++l) sz[l] = hp.levptr[l + 1] - hp.levptr[l];
     p.h_levsize = sz;
     MPK_HIP(hipMemcpyAsync(p.lev_size, p.h_levsize.data(), sizeof(int32_t) * sz.size(),
                            hipMemcpyHostToDevice, s));
   }
-  if (p.div && n > 0)
-    MPK_HIP(hipMemcpyAsync(p.dsrc, hp.dsrc.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   return MPK_OK;
 }
 

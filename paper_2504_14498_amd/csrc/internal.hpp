@@ -116,6 +116,8 @@ struct Ilu0 {
   Plan L, U, UH, LH;
   double *tmp = nullptr;       // [n * C * 4] intermediate of an apply
   int32_t *fac_order = nullptr;  // [n] rows by global forward level (factorisation)
+  int32_t *scan_tmp = nullptr;   // [n / 1024 + 2] block sums of the schedule scans
+  int32_t *t_rp = nullptr, *t_ci = nullptr, *t_src = nullptr;  // A^T pattern (adjoint)
   std::vector<int32_t> h_fac_levptr;
   int32_t *words = nullptr;    // device: [0] abort of standalone applies,
                                // [1] zero-pivot row, [2] non-finite row
@@ -170,14 +172,14 @@ struct HostPlan {
   std::vector<int32_t> order, ptr, col, src, dsrc, seg, seg_level, levptr;
   int32_t nlev = 0;
   int32_t mode = 0, nblk = 0, blk_rows = 0;
-  std::vector<int32_t> blk_r, blk_lev, loc_pos, ell_nd, ell_col, ell_src;
+  std::vector<int32_t> blk_r, blk_lev, loc_pos;
   std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)
 };
 // kind: 0 = L (strict lower of rows, forward), 1 = U (strict upper, backward,
 // divides), 2 = U^H (columns of the upper part, forward, divides),
 // 3 = L^H (columns of the strict lower part, backward).
-void build_plan(const HostCsr &h, const std::vector<int32_t> &diag, int kind, int blk_rows,
-                HostPlan &p);
+// ht: the transposed pattern (needed for kinds 2 and 3 only).
+void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p);
 int default_block_rows(int C, int kmax);
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out);
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);

@@ -133,6 +133,128 @@ static __global__ void check_finite(int64_t n, int C, const int32_t *__restrict_
     }
 }
 
+// ------------------------------------------------- schedule arrays
+// Position of the diagonal entry of each row (the pattern was checked, so
+// every row has one).
+static __global__ void find_diag(int64_t n, const int32_t *__restrict__ rp,
+                                 const int32_t *__restrict__ ci, int32_t *diag) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+    if (ci[q] == i) diag[i] = q;
+}
+
+// Dependencies of the row at each schedule position: the stored columns
+// j < i (lower) or j > i of that row of the given CSR.
+static __global__ void plan_count(int64_t n, const int32_t *__restrict__ order,
+                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                  int lower, int32_t *cnt) {
+  const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (pos >= n) return;
+  const int32_t i = order[pos];
+  int32_t c = 0;
+  for (int32_t q = rp[i]; q < rp[i + 1]; ++q) c += lower ? (ci[q] < i) : (ci[q] > i);
+  cnt[pos] = c;
+}
+
+// Exclusive scan of n counts into out[0..n] (out[n] = total), three
+// phases: 1024-element block scans, a scan of the block sums, offsets.
+constexpr int SCAN_ITEMS = 4, SCAN_BLOCK = BLOCK * SCAN_ITEMS;
+
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
+  __shared__ int32_t sh[BLOCK];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < BLOCK; off <<= 1) {
+    const int32_t t = threadIdx.x >= unsigned(off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int32_t incl = sh[threadIdx.x];
+  *total = sh[BLOCK - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+static __global__ void scan_blocks(int64_t n, const int32_t *__restrict__ in, int32_t *out,
+                                   int32_t *bsum) {
+  const int64_t base = int64_t(blockIdx.x) * SCAN_BLOCK + int64_t(threadIdx.x) * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS], s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  int32_t tot;
+  int32_t run = block_exclusive_scan(s, &tot);
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+static __global__ void scan_sums(int32_t nb, int32_t *bsum) {
+  const int32_t per = (nb + BLOCK - 1) / BLOCK;
+  const int32_t a = threadIdx.x * per, e = min(nb, a + per);
+  int32_t s = 0;
+  for (int32_t q = a; q < e; ++q) s += bsum[q];
+  int32_t tot;
+  int32_t run = block_exclusive_scan(s, &tot);
+  for (int32_t q = a; q < e; ++q) {
+    const int32_t v = bsum[q];
+    bsum[q] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) bsum[nb] = tot;
+}
+
+static __global__ void scan_add(int64_t n, int32_t *out, const int32_t *__restrict__ bsum,
+                                int32_t nb) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i < n) out[i] += bsum[i / SCAN_BLOCK];
+  if (i == 0) out[n] = bsum[nb];
+}
+
+// Per-position dependency arrays: columns and value sources (positions in
+// A's pattern; srcmap maps the rows of A^T back to A) in ascending column
+// order, the flat ELLW slots of the blocked sweeps, and the pivot position.
+static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
+                                 const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const int32_t *__restrict__ srcmap, int lower,
+                                 const int32_t *__restrict__ ptr, int32_t *col, int32_t *src,
+                                 int32_t *ell_nd, int32_t *ell_col, int32_t *ell_src,
+                                 const int32_t *__restrict__ diag, int32_t *dsrc) {
+  const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (pos >= n) return;
+  const int32_t i = order[pos];
+  int32_t o = ptr[pos], d = 0;
+  for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+    const int32_t j = ci[q];
+    if (lower ? j < i : j > i) {
+      const int32_t sp = srcmap ? srcmap[q] : q;
+      col[o] = j;
+      src[o] = sp;
+      if (ell_nd && d < ELLW) {
+        ell_col[pos * ELLW + d] = j;
+        ell_src[pos * ELLW + d] = sp;
+      }
+      ++o;
+      ++d;
+    }
+  }
+  if (ell_nd) {
+    ell_nd[pos] = d;
+    for (int32_t k = d; k < ELLW; ++k) {
+      ell_col[pos * ELLW + k] = 0;
+      ell_src[pos * ELLW + k] = -1;
+    }
+  }
+  if (dsrc) dsrc[pos] = diag[i];
+}
+
 // ------------------------------------------------------ ILU(0) factor
 // One level of the IKJ elimination (Algorithm 1 row by row): for each
 // stored k < i in ascending order, l_ik = a_ik / u_kk, then a_ij -= l_ik *

@@ -4,6 +4,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
+#include <thread>
 
 #include "kernels.hpp"
 
@@ -63,6 +64,12 @@ size_t ilu0_layout(int64_t n, int64_t nnz, int C, int KF, int flags, Bump &b, Il
   }
   m.tmp = b.take<double>(size_t(n) * C * 4);
   m.fac_order = b.take<int32_t>(size_t(n));
+  m.scan_tmp = b.take<int32_t>(size_t(n) / SCAN_BLOCK + 2);
+  if (flags & MPK_ILU0_ADJOINT) {
+    m.t_rp = b.take<int32_t>(size_t(n) + 1);
+    m.t_ci = b.take<int32_t>(size_t(nnz));
+    m.t_src = b.take<int32_t>(size_t(nnz));
+  }
   return b.off;
 }
 
@@ -75,6 +82,35 @@ static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
                        M.fac_order + a, M.row_ptr, M.col_idx, M.diag, M.f, M.words + 1);
   }
   MPK_HIP(hipGetLastError());
+  return MPK_OK;
+}
+
+// Per-position schedule arrays of a plan, built on the device from the
+// uploaded row order (count, scan, fill).
+static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
+  const int64_t n = P.n;
+  const bool tr = kind >= 2;
+  const int32_t *rp = tr ? M.t_rp : M.row_ptr, *ci = tr ? M.t_ci : M.col_idx;
+  const int lower = (kind == 0 || kind == 2) ? 1 : 0;
+  const unsigned g = nblocks(n);
+  // counts land in ptr[0..n), then the scan rewrites ptr in place
+  hipLaunchKernelGGL(plan_count, dim3(g), dim3(BLOCK), 0, s, n, P.order, rp, ci, lower, P.ptr);
+  const int32_t nb = int32_t((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
+  hipLaunchKernelGGL(scan_blocks, dim3(nb), dim3(BLOCK), 0, s, n, (const int32_t *)P.ptr, P.ptr,
+                     M.scan_tmp);
+  hipLaunchKernelGGL(scan_sums, dim3(1), dim3(BLOCK), 0, s, nb, M.scan_tmp);
+  hipLaunchKernelGGL(scan_add, dim3(g), dim3(BLOCK), 0, s, n, P.ptr, (const int32_t *)M.scan_tmp,
+                     nb);
+  const bool ell = P.mode == 1;
+  hipLaunchKernelGGL(plan_fill, dim3(g), dim3(BLOCK), 0, s, n, P.order, rp, ci,
+                     tr ? (const int32_t *)M.t_src : nullptr, lower, (const int32_t *)P.ptr, P.col,
+                     P.src, ell ? P.ell_nd : nullptr, ell ? P.ell_col : nullptr,
+                     ell ? P.ell_src : nullptr, (const int32_t *)M.diag, P.div ? P.dsrc : nullptr);
+  MPK_HIP(hipGetLastError());
+  int32_t tot = 0;
+  MPK_HIP(hipMemcpyAsync(&tot, P.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  P.nnz = tot;
   return MPK_OK;
 }
 
@@ -136,31 +172,61 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     return st;
   }
   MPK_PHASE("check pattern+values");
-  std::vector<int32_t> diag;
-  host_diag(h, diag);
-  HostPlan hp[4];
+  hipLaunchKernelGGL(find_diag, dim3(nblocks(A->n)), dim3(BLOCK), 0, s, A->n, A->row_ptr,
+                     A->col_idx, M->diag);
   const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
   const int br = default_block_rows(C, kmax);
-  build_plan(h, diag, 0, br, hp[0]);
-  build_plan(h, diag, 1, br, hp[1]);
-  if (flags & MPK_ILU0_ADJOINT) {
-    build_plan(h, diag, 2, br, hp[2]);
-    build_plan(h, diag, 3, br, hp[3]);
+  HostPlan hp[4];
+  HostCsr ht;
+  const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
+  {
+    // the schedules of the two (four) sweeps are independent: build them on
+    // separate host threads
+    std::thread t1([&] { build_plan(h, nullptr, 1, br, hp[1]); });
+    std::thread t2;
+    if (adj) {
+      t2 = std::thread([&] {
+        std::vector<int32_t> tsrc;
+        ht.n = h.n;
+        ht.nnz = h.nnz;
+        host_transpose(h, ht.rp, ht.ci, tsrc);
+        std::thread t4([&] { build_plan(h, &ht, 3, br, hp[3]); });
+        build_plan(h, &ht, 2, br, hp[2]);
+        t4.join();
+      });
+    }
+    build_plan(h, nullptr, 0, br, hp[0]);
+    t1.join();
+    if (adj) t2.join();
   }
   MPK_PHASE("build plans (host)");
   M->h_fac_levptr = hp[0].glob_levptr;
   MPK_HIP(hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
                          hipMemcpyHostToDevice, s));
-  MPK_HIP(hipMemcpyAsync(M->diag, diag.data(), sizeof(int32_t) * A->n, hipMemcpyHostToDevice, s));
+  Plan *P[4] = {&M->L, &M->U, &M->UH, &M->LH};
+  for (int k = 0; k < (adj ? 4 : 2); ++k) P[k]->n = A->n;
   if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
   M->U.div = true;
   M->L.div = false;
   M->L.kmax = M->U.kmax = M->UH.kmax = M->LH.kmax = kmax;
-  if (flags & MPK_ILU0_ADJOINT) {
+  if (adj) {
+    // transposed pattern for the adjoint schedules: rows of A^T with the
+    // source position of each entry in A's pattern
+    std::vector<int32_t> trp, tci, tsrc;
+    host_transpose(h, trp, tci, tsrc);
+    MPK_HIP(hipMemcpyAsync(M->t_rp, trp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice, s));
+    MPK_HIP(hipMemcpyAsync(M->t_ci, tci.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));
+    MPK_HIP(hipMemcpyAsync(M->t_src, tsrc.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));
     if ((st = upload_plan(hp[2], M->UH, s)) || (st = upload_plan(hp[3], M->LH, s))) return st;
     M->UH.div = true;
     M->LH.div = false;
     M->UH.conj = M->LH.conj = true;
+    for (int k = 0; k < 4; ++k)
+      if ((st = device_plan_arrays(*P[k], *M, k, s))) return st;
+    MPK_HIP(hipStreamSynchronize(s));
+  } else {
+    for (int k = 0; k < 2; ++k)
+      if ((st = device_plan_arrays(*P[k], *M, k, s))) return st;
   }
   MPK_PHASE("upload plans");
   int32_t init[3] = {0, INT_MAX, INT_MAX};

@@ -164,6 +164,28 @@ int mpk_zkrylov_solve(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel, do
                       int64_t max_iter, const mpk_csr *A, const double *b, double *x, void *ws,
                       size_t ws_bytes, mpk_info *info, void *stream);
 
+/* --------------------------------------------------------- batched solve
+ * nsys independent real systems A[q] x[q] = b[q] of any sizes, each solved
+ * by ILU(0)-preconditioned BiCGSTAB (the only method offered batched) with
+ * the semantics of mpk_dkrylov_solve, in ONE persistent kernel launch: a
+ * workgroup takes the next system, checks its pattern, builds its level
+ * schedules, factors it (Algorithm 1) and runs the passes with the
+ * substitutions of Algorithm 2, synchronising only inside the workgroup.
+ * A, b, x: host arrays of nsys entries holding device pointers.  info: host
+ * array of nsys reports (may be NULL).  schedule: NULL = autotune (on the
+ * first call for a batch shape a few passes of each candidate schedule are
+ * timed, x untouched, and the fastest is cached), or "grid=<workgroups>,
+ * order=lpt|given" (lpt: systems handed out largest first).  Schedules only
+ * map systems to workgroups; results are bitwise identical for every
+ * schedule.  Returns MPK_OK when every system converged, otherwise the most
+ * severe per-system status.  Synchronous. */
+size_t mpk_krylov_batched_workspace_bytes(mpk_method m, mpk_prec vp, mpk_prec fp, int32_t nsys,
+                                          const mpk_csr *A);
+int mpk_dkrylov_solve_batched(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel,
+                              double tol_abs, int64_t max_iter, int32_t nsys, const mpk_csr *A,
+                              const double *const *b, double *const *x, void *ws, size_t ws_bytes,
+                              mpk_info *info, const char *schedule, void *stream);
+
 /* --------------------------------------------------------- inner product
  * out = <a, b> = sum_i conj(a_i) b_i in the working precision (the inner
  * products of Algorithm 3), reduced by a fixed tree (deterministic for a

@@ -1,0 +1,698 @@
+// batched.hip -- many independent systems of uneven size solved by ILU(0)-
+// preconditioned BiCGSTAB in one persistent launch.
+//
+// A persistent workgroup takes the next system from a ticket (systems are
+// handed out in a schedule-defined order, largest first by default) and
+// does everything for it: pattern checks, forward and backward level
+// analysis, the ILU(0) factorisation (Algorithm 1, level by level, IKJ rows)
+// and the BiCGSTAB passes with the ILU(0) substitutions (Algorithm 2, level
+// by level).  All synchronisation is a workgroup barrier, so the systems
+// never wait on one another.  The per-row arithmetic is the single-system
+// path's; the inner products use a fixed 256-thread tree, so any schedule
+// (grid size, system order) gives bitwise-identical results.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace mpk {
+
+// Per-system descriptor (device array).
+struct BSys {
+  int64_t n, nnz;
+  const int32_t *rp, *ci;
+  const double *val, *b;
+  double *x;
+  double *f;          // factor values [nnz * KF]
+  int32_t *diag;      // [n]
+  int32_t *lvl;       // [n] level scratch
+  int32_t *ordL, *ordU;    // [n] rows by forward / backward level
+  int32_t *lptL, *lptU;    // [n + 2] level pointers
+  int32_t *cur;       // [n + 2] scatter cursors
+  double *vec;        // 9 vectors of n * K doubles
+};
+
+// Per-system result (device array).
+struct BOut {
+  int64_t iters, bad_row;
+  int32_t status, pad;
+  double relres_recursive, relres_true;
+};
+
+constexpr int NBV = 9;  // r, r~, p, p^, v, s, s^, t, x (working copy)
+
+// Shared scalars of the system being solved.
+template <int K> struct BShared {
+  int32_t sys, flag, nlevL, nlevU, bad;
+  double nr0sq, nbsq, nr2;
+  double rho[K], alpha[K], omega[K], beta[K];
+  double d[2][K];
+};
+
+__device__ __forceinline__ bool bstop(double nr2, double nr0sq, double er, double ea) {
+  return sqrt(nr2) < er * sqrt(nr0sq) + ea;
+}
+
+// Block-wide sum of two K-limb values per thread, fixed order; result in
+// thread 0 (written to sh).
+template <int K>
+__device__ __forceinline__ void bsum2(mp<K> a, mp<K> b, double (&out)[2][K]) {
+  el<1, K> d[2];
+  d[0].c[0] = a;
+  d[1].c[0] = b;
+  block_reduce<1, K, 2>(d, nullptr);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      out[0][k] = d[0].c[0].v[k];
+      out[1][k] = d[1].c[0].v[k];
+    }
+  }
+  __syncthreads();
+}
+
+// Levels of one sweep, in chunks of BLOCK consecutive rows in the sweep's
+// order: dependencies outside the chunk are final; those inside it are
+// iterated to a fixed point (a chain inside the chunk needs one round per
+// link).  Then rows are bucketed by level (counting sort; the order inside
+// a level is irrelevant because its rows are independent).
+__device__ void blevels(const BSys &S, bool lower, int32_t *ord, int32_t *lpt, int32_t *nlev_out) {
+  __shared__ int32_t tl[BLOCK];
+  __shared__ int32_t changed, maxl;
+  const int64_t n = S.n;
+  const int tid = threadIdx.x;
+  if (tid == 0) maxl = 0;
+  for (int64_t c = 0; c < n; c += BLOCK) {
+    // chunk rows in sweep order
+    const int64_t t = c + tid;
+    const int64_t i = lower ? t : n - 1 - t;
+    const bool valid = t < n;
+    int32_t ext = 0;
+    if (valid) {
+      for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+        const int32_t j = S.ci[q];
+        const bool dep = lower ? j < i : j > i;
+        const int64_t tj = lower ? j : n - 1 - j;
+        if (dep && tj < c) ext = max(ext, S.lvl[j] + 1);
+      }
+    }
+    tl[tid] = ext;
+    __syncthreads();
+    for (;;) {
+      if (tid == 0) changed = 0;
+      __syncthreads();
+      int32_t l = ext;
+      if (valid) {
+        for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+          const int32_t j = S.ci[q];
+          const bool dep = lower ? j < i : j > i;
+          const int64_t tj = lower ? j : n - 1 - j;
+          if (dep && tj >= c) l = max(l, tl[tj - c] + 1);
+        }
+      }
+      __syncthreads();
+      if (valid && l != tl[tid]) {
+        tl[tid] = l;
+        changed = 1;
+      }
+      __syncthreads();
+      if (!changed) break;
+    }
+    if (valid) {
+      S.lvl[i] = tl[tid];
+      atomicMax(&maxl, tl[tid]);
+    }
+    __syncthreads();
+  }
+  const int32_t nlev = maxl + 1;
+  for (int64_t l = tid; l <= nlev; l += BLOCK) lpt[l] = 0;
+  __syncthreads();
+  for (int64_t i = tid; i < n; i += BLOCK) atomicAdd(&lpt[S.lvl[i] + 1], 1);
+  __syncthreads();
+  if (tid == 0) {
+    for (int32_t l = 0; l < nlev; ++l) lpt[l + 1] += lpt[l];
+  }
+  __syncthreads();
+  for (int64_t l = tid; l < nlev; l += BLOCK) S.cur[l] = lpt[l];
+  __syncthreads();
+  for (int64_t i = tid; i < n; i += BLOCK) ord[atomicAdd(&S.cur[S.lvl[i]], 1)] = int32_t(i);
+  __syncthreads();
+  *nlev_out = nlev;
+}
+
+template <int KF>
+__device__ void bfactor(const BSys &S, int32_t nlev, int32_t *bad) {
+  const int tid = threadIdx.x;
+  for (int64_t p = tid; p < S.nnz; p += BLOCK) {
+    S.f[p * KF] = S.val[p];
+    if constexpr (KF == 2) S.f[p * KF + 1] = 0.0;
+  }
+  __syncthreads();
+  for (int32_t l = 0; l < nlev; ++l) {
+    for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK) {
+      const int32_t i = S.ordL[pos];
+      const int32_t ri_end = S.rp[i + 1];
+      for (int32_t p = S.rp[i]; p < ri_end && S.ci[p] < i; ++p) {
+        const int32_t k = S.ci[p];
+        el<1, KF> lik = el_load<1, KF>(S.f + size_t(p) * KF);
+        lik = el_div_k<1, KF, KF>(lik, S.f + size_t(S.diag[k]) * KF);
+        el_store<1, KF>(S.f + size_t(p) * KF, lik);
+        int32_t r = p + 1;
+        for (int32_t q = S.diag[k] + 1; q < S.rp[k + 1]; ++q) {
+          const int32_t j = S.ci[q];
+          while (r < ri_end && S.ci[r] < j) ++r;
+          if (r < ri_end && S.ci[r] == j) {
+            el<1, KF> aij = el_load<1, KF>(S.f + size_t(r) * KF);
+            el<1, KF> prod = el_mul_f<1, KF, KF>(S.f + size_t(q) * KF, lik);
+            el_store<1, KF>(S.f + size_t(r) * KF, el_sub<1, KF>(aij, prod));
+          }
+        }
+      }
+      if (el_is_zero<1, KF>(el_load<1, KF>(S.f + size_t(S.diag[i]) * KF))) atomicMin(bad, i);
+    }
+    __syncthreads();
+  }
+}
+
+// z = (L U)^{-1} r with the level orders; y (intermediate) and z are
+// vectors of the system.  Row arithmetic as Algorithm 2.
+template <int K, int KF>
+__device__ void bapply(const BSys &S, const BShared<K> &sh, const double *r, double *y, double *z) {
+  const int tid = threadIdx.x;
+  for (int32_t l = 0; l < sh.nlevL; ++l) {
+    for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK) {
+      const int32_t i = S.ordL[pos];
+      el<1, K> acc = el_load<1, K>(r + size_t(i) * K);
+      for (int32_t p = S.rp[i]; p < S.rp[i + 1] && S.ci[p] < i; ++p)
+        acc = el_sub<1, K>(acc, el_mul_f<1, K, KF>(S.f + size_t(p) * KF,
+                                                   el_load<1, K>(y + size_t(S.ci[p]) * K)));
+      el_store<1, K>(y + size_t(i) * K, acc);
+    }
+    __syncthreads();
+  }
+  for (int32_t l = 0; l < sh.nlevU; ++l) {
+    for (int32_t pos = S.lptU[l] + tid; pos < S.lptU[l + 1]; pos += BLOCK) {
+      const int32_t i = S.ordU[pos];
+      el<1, K> acc = el_load<1, K>(y + size_t(i) * K);
+      for (int32_t p = S.diag[i] + 1; p < S.rp[i + 1]; ++p)
+        acc = el_sub<1, K>(acc, el_mul_f<1, K, KF>(S.f + size_t(p) * KF,
+                                                   el_load<1, K>(z + size_t(S.ci[p]) * K)));
+      acc = el_div_k<1, K, KF>(acc, S.f + size_t(S.diag[i]) * KF);
+      el_store<1, K>(z + size_t(i) * K, acc);
+    }
+    __syncthreads();
+  }
+}
+
+template <int K>
+__device__ __forceinline__ mp<K> bspmv_row(const BSys &S, int64_t i, const double *x) {
+  return row_spmv<1, K>(i, S.rp, S.ci, S.val, x).c[0];
+}
+
+template <int K> __device__ __forceinline__ mp<K> ldk(const double *p, int64_t i) {
+  mp<K> v;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v.v[k] = p[size_t(i) * K + k];
+  return v;
+}
+template <int K> __device__ __forceinline__ void stk(double *p, int64_t i, const mp<K> &v) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) p[size_t(i) * K + k] = v.v[k];
+}
+template <int K> __device__ __forceinline__ mp<K> shk(const double (&a)[K]) {
+  mp<K> v;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v.v[k] = a[k];
+  return v;
+}
+template <int K> __device__ __forceinline__ void setk(double (&a)[K], const mp<K> &v) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) a[k] = v.v[k];
+}
+
+// Residual r = b - A x (stored when r != nullptr), with ||r||^2 and ||b||^2.
+template <int K>
+__device__ void bresidual(const BSys &S, BShared<K> &sh, const double *x, double *r, double *r2) {
+  mp<K> a = mp_zero<K>(), c = mp_zero<K>();
+  for (int64_t i = threadIdx.x; i < S.n; i += BLOCK) {
+    mp<K> bi = ldk<K>(S.b, i);
+    mp<K> ri = sub<K>(bi, bspmv_row<K>(S, i, x));
+    if (r) stk<K>(r, i, ri);
+    if (r2) stk<K>(r2, i, ri);
+    mp<K> t1 = mul<K>(ri, ri), t2 = mul<K>(bi, bi);
+    a = (i == int64_t(threadIdx.x)) ? t1 : add<K>(a, t1);
+    c = (i == int64_t(threadIdx.x)) ? t2 : add<K>(c, t2);
+  }
+  bsum2<K>(a, c, sh.d);
+}
+
+template <int K, int KF>
+__global__ __launch_bounds__(BLOCK) void batched_bicgstab(const BSys *__restrict__ sys,
+                                                          const int32_t *__restrict__ perm,
+                                                          int32_t nsys, int32_t *ticket,
+                                                          BOut *out, double er, double ea,
+                                                          int64_t max_iter, int copy_x) {
+  __shared__ BShared<K> sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      const int32_t t = atomicAdd(ticket, 1);
+      sh.sys = t < nsys ? perm[t] : -1;
+    }
+    __syncthreads();
+    if (sh.sys < 0) break;
+    const BSys S = sys[sh.sys];
+    BOut o{};
+    o.bad_row = -1;
+    o.relres_true = -1.0;
+    // ---- pattern checks: sorted unique columns, diagonal stored, finite
+    if (tid == 0) sh.bad = INT_MAX, sh.flag = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < S.n; i += BLOCK) {
+      int32_t dg = -1, code = 0;
+      for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+        const int32_t j = S.ci[q];
+        if (j < 0 || j >= S.n || (q > S.rp[i] && j <= S.ci[q - 1])) code = 1;
+        if (j == i) dg = q;
+        const double v = S.val[q];
+        if (!(v - v == 0.0)) code = code ? code : 3;
+      }
+      if (dg < 0 && !code) code = 2;
+      S.diag[i] = dg;
+      if (code) {
+        atomicMin(&sh.bad, int32_t(i));
+        atomicMax(&sh.flag, code);
+      }
+    }
+    __syncthreads();
+    if (sh.flag) {
+      if (tid == 0) {
+        o.status = sh.flag == 1 ? MPK_EPATTERN : (sh.flag == 2 ? MPK_ENO_DIAG : MPK_ENONFINITE);
+        o.bad_row = sh.bad;
+        out[sh.sys] = o;
+      }
+      __syncthreads();
+      continue;
+    }
+    // ---- analysis and factorisation
+    if constexpr (KF > 0) {
+      int32_t nl;
+      blevels(S, true, S.ordL, S.lptL, &nl);
+      if (tid == 0) sh.nlevL = nl;
+      blevels(S, false, S.ordU, S.lptU, &nl);
+      if (tid == 0) sh.nlevU = nl, sh.bad = INT_MAX;
+      __syncthreads();
+      bfactor<KF>(S, sh.nlevL, &sh.bad);
+      __syncthreads();
+      if (sh.bad != INT_MAX) {
+        if (tid == 0) {
+          o.status = MPK_EZERO_PIVOT;
+          o.bad_row = sh.bad;
+          out[sh.sys] = o;
+        }
+        __syncthreads();
+        continue;
+      }
+    }
+    // ---- BiCGSTAB (right-preconditioned, shadow r~ = r0)
+    const int64_t n = S.n;
+    double *r = S.vec, *rt = S.vec + n * K, *p = S.vec + 2 * n * K, *ph = S.vec + 3 * n * K,
+           *v = S.vec + 4 * n * K, *sv = S.vec + 5 * n * K, *shv = S.vec + 6 * n * K,
+           *t = S.vec + 7 * n * K, *xw = S.vec + 8 * n * K;
+    if (KF == 0) {
+      ph = p;
+      shv = sv;
+    }
+    for (int64_t i = tid; i < n * K; i += BLOCK) xw[i] = S.x[i];
+    __syncthreads();
+    bresidual<K>(S, sh, xw, r, rt);
+    if (tid == 0) {
+      sh.nr0sq = sh.d[0][0];
+      sh.nbsq = sh.d[1][0];
+      sh.nr2 = sh.nr0sq;
+      for (int k = 0; k < K; ++k) sh.rho[k] = sh.d[0][k];
+      sh.flag = 0;
+    }
+    __syncthreads();
+    int status = MPK_NOT_CONVERGED;
+    int64_t it = 0;
+    double true_nr2 = -1.0;
+    if (is_zero<K>(shk<K>(sh.rho))) {
+      status = MPK_BREAKDOWN;
+      it = 1;
+    }
+    while (status == MPK_NOT_CONVERGED && it < max_iter) {
+      ++it;
+      // p = r (first pass) or r + beta (p - omega v)
+      for (int64_t i = tid; i < n; i += BLOCK) {
+        mp<K> ri = ldk<K>(r, i);
+        if (it == 1) {
+          stk<K>(p, i, ri);
+        } else {
+          mp<K> tt = sub<K>(ldk<K>(p, i), mul<K>(shk<K>(sh.omega), ldk<K>(v, i)));
+          stk<K>(p, i, add<K>(ri, mul<K>(shk<K>(sh.beta), tt)));
+        }
+      }
+      __syncthreads();
+      if constexpr (KF > 0) bapply<K, KF>(S, sh, p, t, ph);
+      // v = A p^, sigma = <r~, v>
+      {
+        mp<K> a = mp_zero<K>();
+        for (int64_t i = tid; i < n; i += BLOCK) {
+          mp<K> vi = bspmv_row<K>(S, i, ph);
+          stk<K>(v, i, vi);
+          mp<K> tt = mul<K>(ldk<K>(rt, i), vi);
+          a = (i == int64_t(tid)) ? tt : add<K>(a, tt);
+        }
+        bsum2<K>(a, mp_zero<K>(), sh.d);
+      }
+      if (tid == 0) {
+        mp<K> sig = shk<K>(sh.d[0]);
+        sh.flag = is_zero<K>(sig) ? 1 : 0;
+        if (!sh.flag) setk<K>(sh.alpha, div<K>(shk<K>(sh.rho), sig));
+      }
+      __syncthreads();
+      if (sh.flag) {
+        status = MPK_BREAKDOWN;
+        break;
+      }
+      // s = r - alpha v, ||s||^2
+      {
+        mp<K> a = mp_zero<K>();
+        const mp<K> al = shk<K>(sh.alpha);
+        for (int64_t i = tid; i < n; i += BLOCK) {
+          mp<K> si = sub<K>(ldk<K>(r, i), mul<K>(al, ldk<K>(v, i)));
+          stk<K>(sv, i, si);
+          mp<K> tt = mul<K>(si, si);
+          a = (i == int64_t(tid)) ? tt : add<K>(a, tt);
+        }
+        bsum2<K>(a, mp_zero<K>(), sh.d);
+      }
+      const double nr2s = sh.d[0][0];
+      if (bstop(nr2s, sh.nr0sq, er, ea)) {
+        // candidate x + alpha p^ (held in t, unused until A s^) checked on
+        // the true residual
+        const mp<K> al = shk<K>(sh.alpha);
+        for (int64_t i = tid; i < n; i += BLOCK)
+          stk<K>(t, i, add<K>(ldk<K>(xw, i), mul<K>(al, ldk<K>(ph, i))));
+        __syncthreads();
+        bresidual<K>(S, sh, t, nullptr, nullptr);
+        true_nr2 = sh.d[0][0];
+        if (bstop(true_nr2, sh.nr0sq, er, ea)) {
+          for (int64_t i = tid; i < n * K; i += BLOCK) xw[i] = t[i];
+          __syncthreads();
+          if (tid == 0) sh.nr2 = nr2s;
+          status = MPK_OK;
+          break;
+        }
+      }
+      if constexpr (KF > 0) bapply<K, KF>(S, sh, sv, t, shv);
+      // t = A s^, <t, s>, <t, t>
+      {
+        mp<K> a = mp_zero<K>(), c = mp_zero<K>();
+        for (int64_t i = tid; i < n; i += BLOCK) {
+          mp<K> ti = bspmv_row<K>(S, i, shv);
+          stk<K>(t, i, ti);
+          mp<K> t1 = mul<K>(ti, ldk<K>(sv, i)), t2 = mul<K>(ti, ti);
+          a = (i == int64_t(tid)) ? t1 : add<K>(a, t1);
+          c = (i == int64_t(tid)) ? t2 : add<K>(c, t2);
+        }
+        bsum2<K>(a, c, sh.d);
+      }
+      if (tid == 0) {
+        mp<K> tt = shk<K>(sh.d[1]);
+        sh.flag = is_zero<K>(tt) ? 1 : 0;
+        if (!sh.flag) setk<K>(sh.omega, div<K>(shk<K>(sh.d[0]), tt));
+      }
+      __syncthreads();
+      if (sh.flag) {
+        status = MPK_BREAKDOWN;
+        break;
+      }
+      // x = (x + alpha p^) + omega s^; r = s - omega t; ||r||^2, <r~, r>
+      {
+        mp<K> a = mp_zero<K>(), c = mp_zero<K>();
+        const mp<K> al = shk<K>(sh.alpha), om = shk<K>(sh.omega);
+        for (int64_t i = tid; i < n; i += BLOCK) {
+          mp<K> xi = add<K>(ldk<K>(xw, i), mul<K>(al, ldk<K>(ph, i)));
+          stk<K>(xw, i, add<K>(xi, mul<K>(om, ldk<K>(shv, i))));
+          mp<K> ri = sub<K>(ldk<K>(sv, i), mul<K>(om, ldk<K>(t, i)));
+          stk<K>(r, i, ri);
+          mp<K> t1 = mul<K>(ri, ri), t2 = mul<K>(ldk<K>(rt, i), ri);
+          a = (i == int64_t(tid)) ? t1 : add<K>(a, t1);
+          c = (i == int64_t(tid)) ? t2 : add<K>(c, t2);
+        }
+        bsum2<K>(a, c, sh.d);
+      }
+      const double nr2 = sh.d[0][0];
+      mp<K> rho_new = shk<K>(sh.d[1]);
+      __syncthreads();
+      if (tid == 0) sh.nr2 = nr2;
+      if (bstop(nr2, sh.nr0sq, er, ea)) {
+        bresidual<K>(S, sh, xw, nullptr, nullptr);
+        true_nr2 = sh.d[0][0];
+        if (bstop(true_nr2, sh.nr0sq, er, ea)) {
+          status = MPK_OK;
+          break;
+        }
+      }
+      if (is_zero<K>(shk<K>(sh.omega))) {
+        status = MPK_BREAKDOWN;
+        break;
+      }
+      if (it < max_iter && is_zero<K>(rho_new)) {
+        status = MPK_BREAKDOWN;
+        ++it;
+        break;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        mp<K> q1 = div<K>(rho_new, shk<K>(sh.rho));
+        mp<K> q2 = div<K>(shk<K>(sh.alpha), shk<K>(sh.omega));
+        setk<K>(sh.beta, mul<K>(q1, q2));
+        setk<K>(sh.rho, rho_new);
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (copy_x)
+      for (int64_t i = tid; i < n * K; i += BLOCK) S.x[i] = xw[i];
+    if (tid == 0) {
+      o.iters = it;
+      o.status = status;
+      o.relres_recursive = sh.nr0sq > 0 ? sqrt(sh.nr2 / sh.nr0sq) : sqrt(sh.nr2);
+      o.relres_true = true_nr2 < 0 ? -1.0 : (sh.nbsq > 0 ? sqrt(true_nr2 / sh.nbsq) : sqrt(true_nr2));
+      out[sh.sys] = o;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- host side
+struct BLayout {
+  BSys *sys = nullptr;
+  BOut *out = nullptr;
+  int32_t *perm = nullptr;
+  int32_t *ticket = nullptr;
+};
+
+// Workspace: descriptors, results, order, ticket, then per-system arrays.
+static size_t blayout(int32_t nsys, const int64_t *ns, const int64_t *nnzs, int K, int KF, Bump &b,
+                      BLayout *L, std::vector<BSys> *hs) {
+  BLayout tmp;
+  BLayout &l = L ? *L : tmp;
+  l.sys = b.take<BSys>(size_t(nsys));
+  l.out = b.take<BOut>(size_t(nsys));
+  l.perm = b.take<int32_t>(size_t(nsys));
+  l.ticket = b.take<int32_t>(64);
+  for (int32_t q = 0; q < nsys; ++q) {
+    BSys s{};
+    const int64_t n = ns[q], nnz = nnzs[q];
+    s.f = KF ? b.take<double>(size_t(nnz) * KF) : nullptr;
+    s.diag = b.take<int32_t>(size_t(n));
+    s.lvl = b.take<int32_t>(size_t(n));
+    s.ordL = b.take<int32_t>(size_t(n));
+    s.ordU = b.take<int32_t>(size_t(n));
+    s.lptL = b.take<int32_t>(size_t(n) + 2);
+    s.lptU = b.take<int32_t>(size_t(n) + 2);
+    s.cur = b.take<int32_t>(size_t(n) + 2);
+    s.vec = b.take<double>(size_t(NBV) * n * K);
+    s.n = n;
+    s.nnz = nnz;
+    if (hs) hs->push_back(s);
+  }
+  return b.off;
+}
+
+template <int K, int KF>
+static void launch_batched(const BLayout &L, int32_t nsys, unsigned grid, double er, double ea,
+                           int64_t max_iter, int copy_x, hipStream_t s) {
+  hipLaunchKernelGGL((batched_bicgstab<K, KF>), dim3(grid), dim3(BLOCK), 0, s,
+                     (const BSys *)L.sys, (const int32_t *)L.perm, nsys, L.ticket, L.out, er, ea,
+                     max_iter, copy_x);
+}
+
+static int run_batched(int K, int KF, const BLayout &L, int32_t nsys, unsigned grid, double er,
+                       double ea, int64_t max_iter, int copy_x, hipStream_t s) {
+  MPK_HIP(hipMemsetAsync(L.ticket, 0, sizeof(int32_t), s));
+#define MPK_BL(k, kf) \
+  if (K == k && KF == kf) launch_batched<k, kf>(L, nsys, grid, er, ea, max_iter, copy_x, s)
+  MPK_BL(1, 0); MPK_BL(1, 1); MPK_BL(2, 0); MPK_BL(2, 1); MPK_BL(2, 2);
+  MPK_BL(3, 0); MPK_BL(3, 1); MPK_BL(3, 2); MPK_BL(4, 0); MPK_BL(4, 1); MPK_BL(4, 2);
+#undef MPK_BL
+  MPK_HIP(hipGetLastError());
+  return MPK_OK;
+}
+
+// A schedule: the persistent grid size and the order systems are handed
+// out in (largest nnz first, or as given).  Neither changes the arithmetic.
+struct BSched {
+  unsigned grid;
+  bool lpt;
+};
+
+static bool parse_sched(const char *str, BSched &sc) {
+  // "grid=<n>,order=lpt|given"
+  std::string s(str);
+  size_t g = s.find("grid="), o = s.find("order=");
+  if (g == std::string::npos || o == std::string::npos) return false;
+  sc.grid = unsigned(atoi(s.c_str() + g + 5));
+  sc.lpt = s.compare(o + 6, 3, "lpt") == 0;
+  return sc.grid > 0;
+}
+
+static std::map<std::string, BSched> &tune_cache() {
+  static std::map<std::string, BSched> m;
+  return m;
+}
+
+}  // namespace mpk
+
+using namespace mpk;
+
+extern "C" {
+
+size_t mpk_krylov_batched_workspace_bytes(mpk_method m, mpk_prec vp, mpk_prec fp, int32_t nsys,
+                                          const mpk_csr *A) {
+  if (m != MPK_BICGSTAB || vp < MPK_D || vp > MPK_QD || !(fp == 0 || fp == MPK_D || fp == MPK_DD) ||
+      int(fp) > int(vp) || nsys <= 0 || !A)
+    return 0;
+  std::vector<int64_t> ns(static_cast<size_t>(nsys)), nz(static_cast<size_t>(nsys));
+  for (int32_t q = 0; q < nsys; ++q) {
+    if (A[q].n <= 0 || A[q].nnz < 0) return 0;
+    ns[q] = A[q].n;
+    nz[q] = A[q].nnz;
+  }
+  Bump b(nullptr);
+  return blayout(nsys, ns.data(), nz.data(), int(vp), int(fp), b, nullptr, nullptr);
+}
+
+int mpk_dkrylov_solve_batched(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel,
+                              double tol_abs, int64_t max_iter, int32_t nsys, const mpk_csr *A,
+                              const double *const *b, double *const *x, void *ws, size_t ws_bytes,
+                              mpk_info *info, const char *schedule, void *stream) {
+  if (m != MPK_BICGSTAB) return MPK_EUNSUPPORTED;
+  if (vp < MPK_D || vp > MPK_QD || !(fp == 0 || fp == MPK_D || fp == MPK_DD) ||
+      int(fp) > int(vp) || nsys <= 0 || !A || !b || !x || !(tol_rel >= 0) || !(tol_abs >= 0) ||
+      max_iter < 0)
+    return MPK_EINVAL;
+  for (int32_t q = 0; q < nsys; ++q)
+    if (validate_csr_args(&A[q]) || !b[q] || !x[q]) return MPK_EINVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
+      ws_bytes < mpk_krylov_batched_workspace_bytes(m, vp, fp, nsys, A))
+    return MPK_EWORKSPACE;
+  BSched sc{0, true};
+  if (schedule && !parse_sched(schedule, sc)) return MPK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const double t0 = now_ms();
+  const int K = int(vp), KF = int(fp);
+  std::vector<int64_t> ns(static_cast<size_t>(nsys)), nz(static_cast<size_t>(nsys));
+  for (int32_t q = 0; q < nsys; ++q) {
+    ns[q] = A[q].n;
+    nz[q] = A[q].nnz;
+  }
+  Bump bump(ws);
+  BLayout L;
+  std::vector<BSys> hs;
+  blayout(nsys, ns.data(), nz.data(), K, KF, bump, &L, &hs);
+  for (int32_t q = 0; q < nsys; ++q) {
+    hs[q].rp = A[q].row_ptr;
+    hs[q].ci = A[q].col_idx;
+    hs[q].val = A[q].val;
+    hs[q].b = b[q];
+    hs[q].x = x[q];
+  }
+  MPK_HIP(hipMemcpyAsync(L.sys, hs.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+  std::vector<int32_t> lpt(static_cast<size_t>(nsys)), given(static_cast<size_t>(nsys));
+  for (int32_t q = 0; q < nsys; ++q) lpt[q] = given[q] = q;
+  std::stable_sort(lpt.begin(), lpt.end(), [&](int32_t a, int32_t c) { return nz[a] > nz[c]; });
+  int dev = 0;
+  hipDeviceProp_t prop;
+  MPK_HIP(hipGetDevice(&dev));
+  MPK_HIP(hipGetDeviceProperties(&prop, dev));
+  const unsigned cus = unsigned(prop.multiProcessorCount);
+  if (!schedule) {
+    // autotune on the first call for this batch shape: a few passes of each
+    // candidate (x untouched), fastest kept
+    char key[96];
+    int64_t tot = 0;
+    for (auto v : nz) tot += v;
+    snprintf(key, sizeof key, "%d/%lld/%d/%d", nsys, (long long)(tot >> 16), K, KF);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      sc = it->second;
+    } else {
+      const BSched cand[] = {{cus, true}, {2 * cus, true}, {4 * cus, true}, {2 * cus, false}};
+      double best = 1e300;
+      for (const BSched &c : cand) {
+        MPK_HIP(hipMemcpyAsync(L.perm, (c.lpt ? lpt : given).data(), sizeof(int32_t) * nsys,
+                               hipMemcpyHostToDevice, s));
+        MPK_HIP(hipStreamSynchronize(s));
+        const double a = now_ms();
+        int st = run_batched(K, KF, L, nsys, std::min<unsigned>(c.grid, unsigned(nsys)), tol_rel,
+                             tol_abs, std::min<int64_t>(max_iter, 3), 0, s);
+        if (st) return st;
+        MPK_HIP(hipStreamSynchronize(s));
+        const double tm = now_ms() - a;
+        if (tm < best) {
+          best = tm;
+          sc = c;
+        }
+      }
+      tune_cache()[key] = sc;
+    }
+  }
+  MPK_HIP(hipMemcpyAsync(L.perm, (sc.lpt ? lpt : given).data(), sizeof(int32_t) * nsys,
+                         hipMemcpyHostToDevice, s));
+  const double t1 = now_ms();
+  int st = run_batched(K, KF, L, nsys, std::min<unsigned>(sc.grid, unsigned(nsys)), tol_rel,
+                       tol_abs, max_iter, 1, s);
+  if (st) return st;
+  std::vector<BOut> outs(static_cast<size_t>(nsys));
+  MPK_HIP(hipMemcpyAsync(outs.data(), L.out, sizeof(BOut) * nsys, hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  const double t2 = now_ms();
+  int worst = MPK_OK;
+  for (int32_t q = 0; q < nsys; ++q) {
+    if (info) {
+      info[q].iters = outs[q].iters;
+      info[q].bad_row = outs[q].bad_row;
+      info[q].status = outs[q].status;
+      info[q].relres_recursive = outs[q].relres_recursive;
+      info[q].relres_true = outs[q].relres_true;
+      info[q].setup_ms = t1 - t0;
+      info[q].solve_ms = t2 - t1;
+    }
+    if (outs[q].status < 0 && (worst >= 0 || outs[q].status < worst)) worst = outs[q].status;
+    if (outs[q].status > 0 && worst == MPK_OK) worst = outs[q].status;
+  }
+  (void)st;
+  return worst;
+}
+
+}  // extern "C"

@@ -62,6 +62,10 @@ SIGNATURES = [
     ("mpk_krylov_workspace_bytes", _S, [_I, _I, _I, _CSRP, _I]),
     ("mpk_dkrylov_solve", _I, [_I, _I, _I, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP, _P]),
     ("mpk_zkrylov_solve", _I, [_I, _I, _I, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP, _P]),
+    ("mpk_krylov_batched_workspace_bytes", _S, [_I, _I, _I, ctypes.c_int32, _CSRP]),
+    ("mpk_dkrylov_solve_batched", _I, [_I, _I, _I, _D, _D, _I64, ctypes.c_int32, _CSRP,
+                                       ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _S, _INFOP,
+                                       ctypes.c_char_p, _P]),
     ("mpk_dot_workspace_bytes", _S, [_I64, _I, _I]),
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
 ]
@@ -271,3 +275,38 @@ def krylov_solve(method, A, b, x0=None, fprec=1, tol_rel=1e-25, tol_abs=0.0, max
            "hist": hist[: min(hist_len, info.iters)] if hist_len else None,
            "workspace": workspace}
     return x, out
+
+
+def krylov_solve_batched(mats, bs, x0s=None, method="bicgstab", fprec=1, tol_rel=1e-25,
+                         tol_abs=0.0, max_iter=1000, schedule=None, workspace=None, stream=None):
+    """Solve len(mats) independent real systems in one persistent launch.
+    mats: list of Csr; bs: list of (n, 1, K) float64 CUDA tensors.  Returns
+    (list of x, list of info dicts, overall status)."""
+    nsys = len(mats)
+    K = bs[0].shape[2]
+    for A, b in zip(mats, bs):
+        if A.is_complex or _vec_check(A, b, "b") != K:
+            raise ValueError("batched systems must be real with a common precision")
+    xs = [torch.zeros_like(b) if x0s is None else x0s[q].clone() for q, b in enumerate(bs)]
+    arr = (_Csr * nsys)(*[A.c for A in mats])
+    nb = _lib().mpk_krylov_batched_workspace_bytes(METHODS[method], K, fprec, nsys, arr)
+    if nb == 0:
+        raise ValueError("bad batched arguments")
+    if workspace is None or workspace[2] < nb:
+        workspace = _workspace(nb, mats[0].device)
+    ws, ws_ptr, ws_n = workspace
+    bp = (_P * nsys)(*[b.data_ptr() for b in bs])
+    xp = (_P * nsys)(*[x.data_ptr() for x in xs])
+    infos = (_Info * nsys)()
+    st = _lib().mpk_dkrylov_solve_batched(METHODS[method], K, fprec, float(tol_rel),
+                                          float(tol_abs), int(max_iter), nsys, arr, bp, xp,
+                                          ctypes.c_void_p(ws_ptr), ws_n, infos,
+                                          schedule.encode() if schedule else None,
+                                          _stream(stream))
+    out = [{"status": STATUS.get(i.status, i.status), "code": i.status, "iters": i.iters,
+            "relres_recursive": i.relres_recursive, "relres_true": i.relres_true,
+            "bad_row": i.bad_row, "setup_ms": i.setup_ms, "solve_ms": i.solve_ms}
+           for i in infos]
+    if st == -1 or st == -3:
+        raise MpkError(st, "krylov_solve_batched")
+    return xs, out, STATUS.get(st, st), workspace

@@ -1,0 +1,119 @@
+"""GPU parity of the batched persistent solver (one launch, many uneven
+systems): every system against the oracle (true residual and iteration
+count), bitwise identity across schedules, and per-system error reports."""
+import numpy as np
+import pytest
+
+from paper_2504_14498_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_14498_amd import mpk as m
+    m.library()
+    return m
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def batch(nsys=10, seed=7, nmin=500, nmax=12000):
+    rng = np.random.default_rng(seed)
+    probs = [W.random_dd(int(rng.integers(nmin, nmax + 1)), 1000 + q) for q in range(nsys)]
+    probs.append(W.config1(23))          # a stencil in the batch
+    return probs
+
+
+@pytest.fixture(scope="module")
+def solved(mpk, orc):
+    probs = batch()
+    K, tol = 2, 1e-25
+    bs = [orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K)) for p in probs]
+    mats = [mpk.Csr.from_problem(p) for p in probs]
+    xs, infos, st, ws = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
+                                                 tol_rel=tol, max_iter=2000)
+    return probs, bs, mats, xs, infos, st, ws
+
+
+def test_batched_every_system_converges_like_oracle(mpk, orc, solved):
+    probs, bs, mats, xs, infos, st, ws = solved
+    assert st == "ok", infos
+    for p, b, x, info in zip(probs, bs, xs, infos):
+        ref = orc.krylov("bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=1, tol_rel=1e-25,
+                         max_iter=2000)
+        assert ref["status"] == 0
+        assert info["status"] == "ok", (p.name, info)
+        # true residual of the GPU's x, recomputed by the oracle in QD
+        xg = x.cpu().numpy()
+        x4 = np.zeros((p.n, 1, 4))
+        x4[:, :, :2] = xg
+        b4 = np.zeros((p.n, 1, 4))
+        b4[:, :, :2] = b
+        ax = orc.spmv(p.row_ptr, p.col_idx, p.val, x4)
+        r = np.array([[orc.add(b4[i, 0], -ax[i, 0])] for i in range(p.n)])
+        rel = np.sqrt(orc.dot(r, r)[0].sum() / orc.dot(b4, b4)[0].sum())
+        assert rel <= 1.01e-25, (p.name, rel)
+        assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"]), \
+            (p.name, info["iters"], ref["iters"])
+
+
+def test_batched_schedules_bitwise_identical(mpk, solved):
+    probs, bs, mats, xs, infos, st, ws = solved
+    for sched in ("grid=3,order=given", "grid=64,order=lpt", "grid=1,order=lpt"):
+        xs2, infos2, st2, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
+                                                       tol_rel=1e-25, max_iter=2000,
+                                                       schedule=sched, workspace=ws)
+        assert st2 == "ok"
+        for a, b_, i1, i2 in zip(xs, xs2, infos, infos2):
+            assert i1["iters"] == i2["iters"]
+            assert np.array_equal(a.cpu().numpy(), b_.cpu().numpy()), sched
+
+
+def test_batched_matches_single_system_iterations(mpk, orc):
+    p = W.random_dd(5000, 99)
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2))
+    A = mpk.Csr.from_problem(p)
+    x1, i1 = mpk.krylov_solve("bicgstab", A, dev(b), fprec=1, tol_rel=1e-25, max_iter=500)
+    xs, infos, st, _ = mpk.krylov_solve_batched([A], [dev(b)], fprec=1, tol_rel=1e-25,
+                                                max_iter=500)
+    assert st == "ok" and i1["status"] == "ok"
+    assert abs(infos[0]["iters"] - i1["iters"]) <= 2
+
+
+@pytest.mark.parametrize("fprec,K", [(0, 2), (2, 2), (1, 3), (2, 4)])
+def test_batched_precisions(mpk, orc, fprec, K):
+    probs = [W.random_dd(n, 500 + n) for n in (700, 2100, 3300)]
+    tol = {2: 1e-25, 3: 1e-35, 4: 1e-50}[K]
+    bs = [orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K)) for p in probs]
+    mats = [mpk.Csr.from_problem(p) for p in probs]
+    xs, infos, st, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=fprec,
+                                                tol_rel=tol, max_iter=3000)
+    assert st == "ok", infos
+    for p, b, info in zip(probs, bs, infos):
+        ref = orc.krylov("bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=fprec, tol_rel=tol,
+                         max_iter=3000)
+        assert ref["status"] == 0
+        assert info["relres_true"] <= tol
+        assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
+
+
+def test_batched_per_system_errors(mpk, orc):
+    good = W.random_dd(1500, 3)
+    b = orc.spmv(good.row_ptr, good.col_idx, good.val, good.x_true_limbs(2))
+    nodiag = mpk.Csr([0, 2, 3], [0, 1, 0], [1.0, 2.0, 3.0])
+    zeropiv = mpk.Csr([0, 2, 4], [0, 1, 0, 1], [1.0, 1.0, 1.0, 1.0])
+    mats = [mpk.Csr.from_problem(good), nodiag, zeropiv]
+    bs = [dev(b), dev(np.ones((2, 1, 2))), dev(np.ones((2, 1, 2)))]
+    xs, infos, st, _ = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25, max_iter=500,
+                                                schedule="grid=2,order=given")
+    assert infos[0]["status"] == "ok"
+    assert infos[1]["code"] == -5 and infos[1]["bad_row"] == 1
+    assert infos[2]["code"] == -4 and infos[2]["bad_row"] == 1
+    assert st in ("eno_diag", "ezero_pivot")

@@ -177,8 +177,7 @@ def random_dd(n, seed, mmin=7, mmax=30, dmin=1.05, dmax=2.0):
     is d_i * sum |a_ij| with d_i ~ U(dmin, dmax); x_true ~ U(-1, 1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     m = rng.integers(mmin, mmax + 1, size=n)
-    k = m - 1
-    k = np.minimum(k, n - 1)
+    k = np.minimum(m - 1, n - 1)
     tot = int(k.sum())
     rows = np.repeat(np.arange(n, dtype=np.int64), k)
     # draw columns on [0, n-1) and shift past the diagonal, redraw duplicates
@@ -186,7 +185,7 @@ def random_dd(n, seed, mmin=7, mmax=30, dmin=1.05, dmax=2.0):
     cols = cols + (cols >= rows)
     while True:
         key = rows * n + cols
-        order = np.argsort(key, kind="stable")
+        order = np.argsort(key)
         ks = key[order]
         dup = np.zeros(tot, dtype=bool)
         dup[order[1:]] = ks[1:] == ks[:-1]
@@ -200,16 +199,19 @@ def random_dd(n, seed, mmin=7, mmax=30, dmin=1.05, dmax=2.0):
     absum = np.bincount(rows, weights=np.abs(offv), minlength=n)
     diag = d * absum
     diag[diag == 0.0] = 1.0
-    allr = np.concatenate([rows, np.arange(n, dtype=np.int64)])
-    allc = np.concatenate([cols, np.arange(n, dtype=np.int64)])
-    allv = np.concatenate([offv, diag])
-    order = np.lexsort((allc, allr))
-    ci = allc[order].astype(np.int32)
-    val = allv[order]
+    # merge the (already row-grouped) off-diagonal entries, sorted by key,
+    # with the diagonal: one sort of the combined row-major key
+    ks = ks  # sorted off-diagonal keys from the last duplicate check
+    offs = offv[order]
+    dkey = np.arange(n, dtype=np.int64) * (n + 1)
+    pos = np.searchsorted(ks, dkey)
+    allk = np.insert(ks, pos, dkey)
+    allv = np.insert(offs, pos, diag)
+    ci = (allk % n).astype(np.int32)
     rp = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(np.bincount(allr, minlength=n), out=rp[1:])
+    np.cumsum(k + 1, out=rp[1:])
     x = rng.uniform(-1.0, 1.0, n)
-    return Problem("random_dd_%d_s%d" % (n, seed), n, rp.astype(np.int32), ci, val, x,
+    return Problem("random_dd_%d_s%d" % (n, seed), n, rp.astype(np.int32), ci, allv, x,
                    {"tol": 1e-25, "max_iter": 10000, "method": "bicgstab", "kf": 1})
 
 

@@ -57,6 +57,9 @@ def lib():
         L.or_krylov.argtypes = [c_int, i64, _I32, _I32, _D, c_int, c_int, c_int, _D, _D,
                                 dbl, dbl, i64, _I64, _D, _D, _I64, _D, i64]
         L.or_krylov.restype = c_int
+        L.or_krylov_with_factor.argtypes = [c_int, i64, _I32, _I32, _D, c_int, c_int, c_int, _D,
+                                            _D, _D, dbl, dbl, i64, _I64, _D, _D, _I64, _D, i64]
+        L.or_krylov_with_factor.restype = c_int
         _lib = L
     return _lib
 
@@ -215,8 +218,10 @@ def dot(a, b):
 
 
 def krylov(method, rp, ci, val, b, kf, tol_rel, tol_abs=0.0, max_iter=1000, x0=None,
-           hist_len=0):
-    """Run one of the four methods.  b: (n, C, K).  Returns a dict."""
+           hist_len=0, factor=None):
+    """Run one of the four methods.  b: (n, C, K).  Returns a dict.  With
+    ``factor`` (float64 [nnz, C, kf] in A's pattern) that factor is used
+    instead of computing ILU(0)."""
     b = _f64(b)
     n, C, K = b.shape
     rp, ci, val = _csr(rp, ci, val, C)
@@ -226,6 +231,16 @@ def krylov(method, rp, ci, val, b, kf, tol_rel, tol_abs=0.0, max_iter=1000, x0=N
     rt = ctypes.c_double(0)
     bad = ctypes.c_int64(-1)
     hist = np.zeros(max(hist_len, 1))
+    if factor is not None:
+        f = _f64(np.asarray(factor, dtype=np.float64).reshape(len(ci), C, kf))
+        st = lib().or_krylov_with_factor(METHODS[method], n, _i32(rp), _i32(ci), _d(val), C, K,
+                                         kf, _d(f), _d(b), _d(x), float(tol_rel),
+                                         float(tol_abs), int(max_iter), ctypes.byref(iters),
+                                         ctypes.byref(rr), ctypes.byref(rt), ctypes.byref(bad),
+                                         _d(hist), hist_len)
+        return {"status": st, "x": x, "iters": iters.value, "relres_recursive": rr.value,
+                "relres_true": rt.value, "bad_row": bad.value,
+                "hist": hist[: min(hist_len, iters.value)]}
     st = lib().or_krylov(METHODS[method], n, _i32(rp), _i32(ci), _d(val), C, K, kf, _d(b),
                          _d(x), float(tol_rel), float(tol_abs), int(max_iter),
                          ctypes.byref(iters), ctypes.byref(rr), ctypes.byref(rt),

@@ -1251,11 +1251,14 @@ static int run_gpbicg(const sys_t *s, const double *b, double *x, int64_t max_it
  * without a preconditioner; kf = 1, 2 factor A by ILU(0) in that many limbs
  * first.  x holds x_0 on entry.  Returns ST_* (>= 0) or an ILU(0) error
  * (< 0).  hist (optional) receives the leading limb of ||r_k||^2. */
-int or_krylov(int method, int64_t n, const int32_t *rp, const int32_t *ci,
-              const double *val, int C, int K, int kf, const double *b, double *x,
-              double eps_r, double eps_a, int64_t max_iter, int64_t *iters,
-              double *relres_recursive, double *relres_true, int64_t *bad_row,
-              double *hist, int64_t hist_len)
+/* The four methods with the ILU(0) factor either computed here (Alg. 1,
+ * fgiven == NULL) or supplied by the caller in A's pattern (fgiven: nnz x C
+ * x kf values, e.g. a corrected factor); the iteration is the same. */
+static int krylov_impl(int method, int64_t n, const int32_t *rp, const int32_t *ci,
+                       const double *val, int C, int K, int kf, const double *fgiven,
+                       const double *b, double *x, double eps_r, double eps_a,
+                       int64_t max_iter, int64_t *iters, double *relres_recursive,
+                       double *relres_true, int64_t *bad_row, double *hist, int64_t hist_len)
 {
     sys_t s;
     or_info_t info;
@@ -1272,10 +1275,14 @@ int or_krylov(int method, int64_t n, const int32_t *rp, const int32_t *ci,
     *bad_row = -1;
     if (kf > 0) {
         f = (double *)malloc(sizeof(double) * ((size_t)rp[n] * C * kf + 1));
-        st = or_ilu0(n, rp, ci, val, C, kf, f, bad_row);
-        if (st != 0) {
-            free(f);
-            return st;
+        if (fgiven) {
+            memcpy(f, fgiven, sizeof(double) * (size_t)rp[n] * C * kf);
+        } else {
+            st = or_ilu0(n, rp, ci, val, C, kf, f, bad_row);
+            if (st != 0) {
+                free(f);
+                return st;
+            }
         }
     }
     s.f = f;
@@ -1292,4 +1299,25 @@ int or_krylov(int method, int64_t n, const int32_t *rp, const int32_t *ci,
     *relres_true = info.relres_true;
     free(f);
     return st;
+}
+
+int or_krylov(int method, int64_t n, const int32_t *rp, const int32_t *ci,
+              const double *val, int C, int K, int kf, const double *b, double *x,
+              double eps_r, double eps_a, int64_t max_iter, int64_t *iters,
+              double *relres_recursive, double *relres_true, int64_t *bad_row,
+              double *hist, int64_t hist_len)
+{
+    return krylov_impl(method, n, rp, ci, val, C, K, kf, NULL, b, x, eps_r, eps_a, max_iter,
+                       iters, relres_recursive, relres_true, bad_row, hist, hist_len);
+}
+
+int or_krylov_with_factor(int method, int64_t n, const int32_t *rp, const int32_t *ci,
+                          const double *val, int C, int K, int kf, const double *f,
+                          const double *b, double *x, double eps_r, double eps_a,
+                          int64_t max_iter, int64_t *iters, double *relres_recursive,
+                          double *relres_true, int64_t *bad_row, double *hist,
+                          int64_t hist_len)
+{
+    return krylov_impl(method, n, rp, ci, val, C, K, kf, f, b, x, eps_r, eps_a, max_iter,
+                       iters, relres_recursive, relres_true, bad_row, hist, hist_len);
 }

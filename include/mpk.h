@@ -164,6 +164,24 @@ int mpk_zkrylov_solve(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel, do
                       int64_t max_iter, const mpk_csr *A, const double *b, double *x, void *ws,
                       size_t ws_bytes, mpk_info *info, void *stream);
 
+/* The same methods with a preconditioner the caller built with
+ * mpk_?ilu0_factor on this A (same row_ptr and col_idx pointers), possibly
+ * changed since by mpk_ilu0_correct: nothing is factored here.  The factor
+ * must have been built with MPK_ILU0_VPREC(k), k >= vp (or 0), and with
+ * MPK_ILU0_ADJOINT for BiCG; otherwise MPK_EINVAL.  The handle's sweeps
+ * use its own workspace, so one factor serves one solve at a time.  The
+ * workspace here holds the vectors only. */
+size_t mpk_krylov_precond_workspace_bytes(mpk_method m, mpk_prec vp, const mpk_csr *A,
+                                          int is_complex);
+int mpk_dkrylov_solve_precond(mpk_method m, mpk_prec vp, const mpk_ilu0 *M, double tol_rel,
+                              double tol_abs, int64_t max_iter, const mpk_csr *A, const double *b,
+                              double *x, void *ws, size_t ws_bytes, mpk_info *info,
+                              void *stream);
+int mpk_zkrylov_solve_precond(mpk_method m, mpk_prec vp, const mpk_ilu0 *M, double tol_rel,
+                              double tol_abs, int64_t max_iter, const mpk_csr *A, const double *b,
+                              double *x, void *ws, size_t ws_bytes, mpk_info *info,
+                              void *stream);
+
 /* --------------------------------------------------------- batched solve
  * nsys independent real systems A[q] x[q] = b[q] of any sizes, each solved
  * by ILU(0)-preconditioned BiCGSTAB (the only method offered batched) with
@@ -185,6 +203,81 @@ int mpk_dkrylov_solve_batched(mpk_method m, mpk_prec vp, mpk_prec fp, double tol
                               double tol_abs, int64_t max_iter, int32_t nsys, const mpk_csr *A,
                               const double *const *b, double *const *x, void *ws, size_t ws_bytes,
                               mpk_info *info, const char *schedule, void *stream);
+
+/* ------------------------------------------- learned ILU(0) correction
+ * Not in the paper: a correction of the binary64 ILU(0) factor (Algorithm
+ * 1) predicted by a small graph network, applied without touching the
+ * methods' arithmetic or their stopping test; plain ILU(0) stays the
+ * fallback.  Real matrices with a binary64 (MPK_D) factor only.
+ *
+ * Graph: nodes are the rows of A, edges its stored entries q = (i, j) in
+ * CSR order, diagonal included, so the output delta[nnz] lies on the
+ * ILU(0) pattern.  Inputs, from A and the plain factor (l below the
+ * diagonal, u on and above it):
+ *   node i: log|a_ii|, sum_{j != i}|a_ij| / |a_ii|, log(|u_ii| / |a_ii|),
+ *           (stored entries of row i) / 8
+ *   edge q: a_ij / |a_ii|, (l_ij if j < i, else u_ij / |a_ii|), [j < i], [j > i]
+ * Network, hidden width 32, three message-passing layers; R() rounds to
+ * bfloat16 (nearest even), the type activations are stored in:
+ *   h_i = R(relu(Wn x_i + bn)),  e_q = R(relu(We y_q + be))
+ *   per layer: m_q = R(relu(Wm [h_i; h_j; e_q] + bm)),
+ *              g_i = R(mean of m_q over row i),
+ *              h_i <- R(h_i + relu(Wu [h_i; g_i] + bu)),  e_q <- R(e_q + m_q)
+ *   delta_q = wd . [h_i; h_j; e_q] + bd
+ * Wm and Wu are rounded to bfloat16 for the matrix cores (float32
+ * accumulation); the encoders and the decoder use the float32 weights.
+ * Parameters: one float32 vector of mpk_gnn_param_count() = 15969 values,
+ * row-major [out][in]: Wn[32][4], bn[32], We[32][4], be[32], then per layer
+ * Wm[32][96], bm[32], Wu[32][64], bu[32], then wd[96], bd[1].
+ *
+ * Correction: u_ii <- u_ii exp(delta_ii) (sign kept, never zero); every
+ * other value v <- v (1 + tanh(delta_q) / 2).
+ *
+ * All device pointers; all calls on `stream`; setup, loss (its host part)
+ * and correct synchronize, forward, backward and adam are asynchronous. */
+int64_t mpk_gnn_param_count(void);
+/* Initial parameters from seed: weights uniform in +-1/sqrt(fan_in), biases
+ * zero, decoder zero (so the first prediction is delta = 0, the plain
+ * factor). */
+int mpk_gnn_init(float *params, uint64_t seed, void *stream);
+/* Per-matrix graph data (edge rows, transposed pattern, inputs), built
+ * from A and its plain binary64 factor M (from mpk_dilu0_factor on this
+ * A, before any correction).  graph: caller-owned, 256-byte aligned, at
+ * least mpk_gnn_graph_bytes(A). */
+size_t mpk_gnn_graph_bytes(const mpk_csr *A);
+int mpk_gnn_graph_setup(const mpk_csr *A, const mpk_ilu0 *M, void *graph, size_t graph_bytes,
+                        void *stream);
+/* delta[nnz] (float32) = network(params) on a set-up graph.  ws (at least
+ * mpk_gnn_workspace_bytes(A)) keeps the activations for backward. */
+size_t mpk_gnn_workspace_bytes(const mpk_csr *A);
+int mpk_gnn_forward(const mpk_csr *A, const void *graph, const float *params, float *delta,
+                    void *ws, size_t ws_bytes, void *stream);
+/* dparams = d(sum_q ddelta_q delta_q)/dparams for the activations the last
+ * forward left in ws (bfloat16 rounding taken as the identity).  Writes
+ * (does not accumulate) all mpk_gnn_param_count() values. */
+int mpk_gnn_backward(const mpk_csr *A, const void *graph, const float *params,
+                     const float *ddelta, float *dparams, void *ws, size_t ws_bytes,
+                     void *stream);
+/* Training loss of a correction delta on probe vectors w_p (nprobe rows of
+ * n doubles, e.g. normalised residuals of the plain method), in binary64:
+ *   loss = mean_p ||A w_p - L~ U~ w_p||^2 / ||A w_p||^2
+ * with L~ (unit lower) and U~ from the plain factor M corrected by delta
+ * as above.  loss: device double; ddelta (may be NULL): d loss / d delta as
+ * float32.  M must be uncorrected. */
+size_t mpk_gnn_loss_workspace_bytes(const mpk_csr *A, int32_t nprobe);
+int mpk_gnn_factor_loss(const mpk_csr *A, const mpk_ilu0 *M, const void *graph,
+                        const float *delta, int32_t nprobe, const double *probes, double *loss,
+                        float *ddelta, void *ws, size_t ws_bytes, void *stream);
+/* One Adam step (Kingma and Ba, with bias correction) over count values;
+ * step counts from 1. */
+int mpk_gnn_adam(int64_t count, int64_t step, float lr, float beta1, float beta2, float eps,
+                 float *params, const float *grad, float *m, float *v, void *stream);
+/* Apply delta to the factor in place (and to its sweep schedules), with
+ * guards: if any delta or corrected value is non-finite, or a pivot ratio
+ * exp(delta_ii) falls outside [1e-8, 1e8], nothing changes and
+ * *fell_back (host int) = 1; otherwise 0.  Corrections compound if called
+ * twice.  Synchronous. */
+int mpk_ilu0_correct(mpk_ilu0 *M, const float *delta, int32_t *fell_back, void *stream);
 
 /* --------------------------------------------------------- inner product
  * out = <a, b> = sum_i conj(a_i) b_i in the working precision (the inner

@@ -127,6 +127,9 @@ struct Ilu0 {
 size_t ilu0_layout(int64_t n, int64_t nnz, int C, int KF, int flags, Bump &b, Ilu0 *M);
 int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
                      Ilu0 *M, mpk_info *info, hipStream_t s);
+// Re-gather the sweep plans' values after the factor values in A's pattern
+// changed (same pattern).
+int ilu0_regather(const Ilu0 &M, hipStream_t s);
 int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z,
                       int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
                       hipStream_t s);

@@ -549,15 +549,17 @@ static int nvec_for(int method) {
   }
 }
 
+// ext_ilu: the preconditioner is a caller's factor, so no ILU(0) part.
 static size_t krylov_layout(int method, int C, int K, int KF, int64_t n, int64_t nnz, Bump &b,
-                            Layout *L) {
+                            Layout *L, bool ext_ilu = false) {
   Layout tmp;
   Layout &l = L ? *L : tmp;
   l.st = b.take<KState>(1);
   l.abort = b.take<int32_t>(64);
   l.partials = b.take<double>(size_t(nblocks(n)) * 6 * C * K);
   for (int q = 0; q < nvec_for(method); ++q) l.v[q] = b.take<double>(size_t(n) * C * K);
-  if (KF > 0) ilu0_layout(n, nnz, C, KF, method == MPK_BICG ? MPK_ILU0_ADJOINT : 0, b, &l.ilu);
+  if (KF > 0 && !ext_ilu)
+    ilu0_layout(n, nnz, C, KF, method == MPK_BICG ? MPK_ILU0_ADJOINT : 0, b, &l.ilu);
   if (method == MPK_BICG) {
     l.t_rp = b.take<int32_t>(size_t(n) + 1);
     l.t_ci = b.take<int32_t>(size_t(nnz));
@@ -731,7 +733,7 @@ static bool use_graph(hipStream_t s) {
 template <int C, int K>
 static int krylov_run(int method, int KF, double tol_rel, double tol_abs, int64_t max_iter,
                       const mpk_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-                      mpk_info *info, hipStream_t s) {
+                      mpk_info *info, hipStream_t s, const Ilu0 *ext = nullptr) {
   const double t0 = now_ms();
   Solver<C, K> S;
   S.method = method;
@@ -743,10 +745,15 @@ static int krylov_run(int method, int KF, double tol_rel, double tol_abs, int64_
   S.precond = KF > 0;
   S.nblk = int(nblocks(A->n));
   Bump bump(ws);
-  if (krylov_layout(method, C, K, KF, A->n, A->nnz, bump, &S.L) > ws_bytes) return MPK_EWORKSPACE;
+  if (krylov_layout(method, C, K, KF, A->n, A->nnz, bump, &S.L, ext != nullptr) > ws_bytes)
+    return MPK_EWORKSPACE;
   int st;
   int64_t bad = -1;
-  if (KF > 0) {
+  if (ext) {
+    // a factor the caller built (and possibly corrected) on A's pattern; its
+    // values were checked when it was factored
+    S.L.ilu = *ext;
+  } else if (KF > 0) {
     mpk_info finfo{};
     // the ILU(0) part of the workspace starts at its first array; carving it
     // again from there reproduces the same offsets
@@ -856,9 +863,46 @@ static int krylov_run(int method, int KF, double tol_rel, double tol_abs, int64_
   return status;
 }
 
-static size_t krylov_bytes(int method, int C, int K, int KF, int64_t n, int64_t nnz) {
+static size_t krylov_bytes(int method, int C, int K, int KF, int64_t n, int64_t nnz,
+                           bool ext_ilu = false) {
   Bump b(nullptr);
-  return krylov_layout(method, C, K, KF, n, nnz, b, nullptr);
+  return krylov_layout(method, C, K, KF, n, nnz, b, nullptr, ext_ilu);
+}
+
+// Solve with a factor the caller owns (from mpk_?ilu0_factor, possibly
+// corrected): same iteration, no factorisation inside.
+static int krylov_solve_precond(int C, mpk_method m, mpk_prec vp, const mpk_ilu0 *Mh,
+                                double tol_rel, double tol_abs, int64_t max_iter,
+                                const mpk_csr *A, const double *b, double *x, void *ws,
+                                size_t ws_bytes, mpk_info *info, void *stream) {
+  if (info) {
+    info->iters = 0;
+    info->bad_row = -1;
+    info->relres_recursive = -1;
+    info->relres_true = -1;
+    info->setup_ms = info->solve_ms = 0;
+  }
+  const Ilu0 *M = reinterpret_cast<const Ilu0 *>(Mh);
+  int st = validate_csr_args(A);
+  if (!st && (m < MPK_BICG || m > MPK_GPBICG || vp < MPK_D || vp > MPK_QD || !b || !x || !M ||
+              !(tol_rel >= 0) || !(tol_abs >= 0) || max_iter < 0))
+    st = MPK_EINVAL;
+  // the factor must belong to A, hold enough limbs for K and, for BiCG,
+  // carry the adjoint sweeps
+  if (!st && (M->C != C || M->n != A->n || M->nnz != A->nnz || M->row_ptr != A->row_ptr ||
+              M->col_idx != A->col_idx || M->KF > int(vp) || M->L.kmax < int(vp) ||
+              M->U.kmax < int(vp) || (m == MPK_BICG && !(M->flags & MPK_ILU0_ADJOINT))))
+    st = MPK_EINVAL;
+  if (!st && (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
+              ws_bytes < krylov_bytes(m, C, int(vp), M->KF, A->n, A->nnz, true)))
+    st = MPK_EWORKSPACE;
+  if (!st)
+    st = dispatch_ck(C, int(vp), [&]<int CC, int KK>() {
+      return krylov_run<CC, KK>(int(m), M->KF, tol_rel, tol_abs, max_iter, A, b, x, ws,
+                                ws_bytes, info, (hipStream_t)stream, M);
+    });
+  if (info) info->status = st;
+  return st;
 }
 
 static int krylov_solve(int C, mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel,
@@ -912,6 +956,30 @@ int mpk_zkrylov_solve(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel, do
                       int64_t max_iter, const mpk_csr *A, const double *b, double *x, void *ws,
                       size_t ws_bytes, mpk_info *info, void *stream) {
   return krylov_solve(2, m, vp, fp, tol_rel, tol_abs, max_iter, A, b, x, ws, ws_bytes, info, stream);
+}
+
+size_t mpk_krylov_precond_workspace_bytes(mpk_method m, mpk_prec vp, const mpk_csr *A,
+                                          int is_complex) {
+  if (!A || A->n <= 0 || A->nnz < 0 || m < MPK_BICG || m > MPK_GPBICG || vp < MPK_D ||
+      vp > MPK_QD)
+    return 0;
+  return krylov_bytes(m, is_complex ? 2 : 1, int(vp), 1, A->n, A->nnz, true);
+}
+
+int mpk_dkrylov_solve_precond(mpk_method m, mpk_prec vp, const mpk_ilu0 *M, double tol_rel,
+                              double tol_abs, int64_t max_iter, const mpk_csr *A, const double *b,
+                              double *x, void *ws, size_t ws_bytes, mpk_info *info,
+                              void *stream) {
+  return krylov_solve_precond(1, m, vp, M, tol_rel, tol_abs, max_iter, A, b, x, ws, ws_bytes,
+                              info, stream);
+}
+
+int mpk_zkrylov_solve_precond(mpk_method m, mpk_prec vp, const mpk_ilu0 *M, double tol_rel,
+                              double tol_abs, int64_t max_iter, const mpk_csr *A, const double *b,
+                              double *x, void *ws, size_t ws_bytes, mpk_info *info,
+                              void *stream) {
+  return krylov_solve_precond(2, m, vp, M, tol_rel, tol_abs, max_iter, A, b, x, ws, ws_bytes,
+                              info, stream);
 }
 
 }  // extern "C"

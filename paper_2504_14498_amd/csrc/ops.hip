@@ -128,6 +128,14 @@ static int gather_plan(const Plan &P, const Ilu0 &M, hipStream_t s) {
   return MPK_OK;
 }
 
+int ilu0_regather(const Ilu0 &M, hipStream_t s) {
+  int st;
+  if ((st = gather_plan(M.L, M, s)) || (st = gather_plan(M.U, M, s))) return st;
+  if (M.flags & MPK_ILU0_ADJOINT)
+    if ((st = gather_plan(M.UH, M, s)) || (st = gather_plan(M.LH, M, s))) return st;
+  return MPK_OK;
+}
+
 static bool timing_on() {
   static const bool on = getenv("MPK_TIMING") != nullptr;
   return on;

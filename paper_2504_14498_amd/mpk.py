@@ -66,6 +66,23 @@ SIGNATURES = [
     ("mpk_dkrylov_solve_batched", _I, [_I, _I, _I, _D, _D, _I64, ctypes.c_int32, _CSRP,
                                        ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _S, _INFOP,
                                        ctypes.c_char_p, _P]),
+    ("mpk_krylov_precond_workspace_bytes", _S, [_I, _I, _CSRP, _I]),
+    ("mpk_dkrylov_solve_precond", _I, [_I, _I, _P, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP,
+                                       _P]),
+    ("mpk_zkrylov_solve_precond", _I, [_I, _I, _P, _D, _D, _I64, _CSRP, _P, _P, _P, _S, _INFOP,
+                                       _P]),
+    ("mpk_gnn_param_count", _I64, []),
+    ("mpk_gnn_init", _I, [_P, ctypes.c_uint64, _P]),
+    ("mpk_gnn_graph_bytes", _S, [_CSRP]),
+    ("mpk_gnn_graph_setup", _I, [_CSRP, _P, _P, _S, _P]),
+    ("mpk_gnn_workspace_bytes", _S, [_CSRP]),
+    ("mpk_gnn_forward", _I, [_CSRP, _P, _P, _P, _P, _S, _P]),
+    ("mpk_gnn_backward", _I, [_CSRP, _P, _P, _P, _P, _P, _S, _P]),
+    ("mpk_gnn_loss_workspace_bytes", _S, [_CSRP, ctypes.c_int32]),
+    ("mpk_gnn_factor_loss", _I, [_CSRP, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _S, _P]),
+    ("mpk_gnn_adam", _I, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, _P, _P, _P, _P, _P]),
+    ("mpk_ilu0_correct", _I, [_P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("mpk_dot_workspace_bytes", _S, [_I64, _I, _I]),
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
 ]
@@ -310,3 +327,136 @@ def krylov_solve_batched(mats, bs, x0s=None, method="bicgstab", fprec=1, tol_rel
     if st == -1 or st == -3:
         raise MpkError(st, "krylov_solve_batched")
     return xs, out, STATUS.get(st, st), workspace
+
+
+def krylov_solve_precond(method, A, M, b, x0=None, tol_rel=1e-25, tol_abs=0.0, max_iter=1000,
+                         hist_len=0, workspace=None, graph=True):
+    """Solve A x = b preconditioned by an existing factor M (an Ilu0 of this
+    A, possibly corrected by ilu0_correct).  Returns (x, info dict)."""
+    K = _vec_check(A, b, "b")
+    if M.A is not A:
+        raise ValueError("the factor belongs to another matrix")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    nb = _lib().mpk_krylov_precond_workspace_bytes(METHODS[method], K, ctypes.byref(A.c),
+                                                   int(A.is_complex))
+    if nb == 0:
+        raise ValueError("bad krylov_solve_precond arguments")
+    if workspace is None or workspace[2] < nb:
+        workspace = _workspace(nb, A.device)
+    ws, ws_ptr, ws_n = workspace
+    hist = torch.zeros(max(hist_len, 1), dtype=torch.float64, device=A.device)
+    info = _Info()
+    info.res_history = hist.data_ptr() if hist_len > 0 else None
+    info.res_history_len = hist_len
+    fn = _lib().mpk_zkrylov_solve_precond if A.is_complex else _lib().mpk_dkrylov_solve_precond
+    cur = torch.cuda.current_stream(A.device)
+    s = _side_stream(A.device) if graph else cur
+    if graph:
+        s.wait_stream(cur)
+    st = fn(METHODS[method], K, M.handle, float(tol_rel), float(tol_abs), int(max_iter),
+            ctypes.byref(A.c), _ptr(b), _ptr(x), ctypes.c_void_p(ws_ptr), ws_n, ctypes.byref(info),
+            ctypes.c_void_p(s.cuda_stream))
+    if graph:
+        cur.wait_stream(s)
+    if st < 0:
+        raise MpkError(st, "krylov_solve_precond")
+    out = {"status": STATUS.get(st, st), "code": st, "iters": info.iters,
+           "relres_recursive": info.relres_recursive, "relres_true": info.relres_true,
+           "setup_ms": info.setup_ms, "solve_ms": info.solve_ms, "bad_row": info.bad_row,
+           "hist": hist[: min(hist_len, info.iters)] if hist_len else None,
+           "workspace": workspace}
+    return x, out
+
+
+# ----------------------------------------------------- learned correction
+
+def gnn_param_count():
+    return int(_lib().mpk_gnn_param_count())
+
+
+def gnn_init(seed, device="cuda", stream=None):
+    """Initial float32 parameter vector (decoder zero: delta = 0)."""
+    p = torch.empty(gnn_param_count(), dtype=torch.float32, device=device)
+    _check(_lib().mpk_gnn_init(_ptr(p), int(seed), _stream(stream)), "gnn_init")
+    return p
+
+
+class GnnGraph:
+    """Graph data of one matrix (edge rows, transposed pattern, network
+    inputs from A and its plain binary64 factor M)."""
+
+    def __init__(self, A, M, stream=None):
+        if A.is_complex or M.fprec != 1:
+            raise ValueError("the learned correction needs a real matrix and a binary64 factor")
+        nb = _lib().mpk_gnn_graph_bytes(ctypes.byref(A.c))
+        self._buf, self.ptr, self.nbytes = _workspace(nb, A.device)
+        self.A = A
+        _check(_lib().mpk_gnn_graph_setup(ctypes.byref(A.c), M.handle, ctypes.c_void_p(self.ptr),
+                                          self.nbytes, _stream(stream)), "gnn_graph_setup")
+
+
+def gnn_workspace(A):
+    return _workspace(_lib().mpk_gnn_workspace_bytes(ctypes.byref(A.c)), A.device)
+
+
+def gnn_forward(G, params, delta=None, workspace=None, stream=None):
+    """delta[nnz] (float32) predicted for G's matrix; returns (delta, ws)."""
+    A = G.A
+    if delta is None:
+        delta = torch.empty(A.nnz, dtype=torch.float32, device=A.device)
+    if workspace is None:
+        workspace = gnn_workspace(A)
+    _, wp, wn = workspace
+    _check(_lib().mpk_gnn_forward(ctypes.byref(A.c), ctypes.c_void_p(G.ptr), _ptr(params),
+                                  _ptr(delta), ctypes.c_void_p(wp), wn, _stream(stream)),
+           "gnn_forward")
+    return delta, workspace
+
+
+def gnn_backward(G, params, ddelta, workspace, dparams=None, stream=None):
+    """Parameter gradient of sum(ddelta * delta) for the last forward in
+    workspace."""
+    A = G.A
+    if dparams is None:
+        dparams = torch.empty_like(params)
+    _, wp, wn = workspace
+    _check(_lib().mpk_gnn_backward(ctypes.byref(A.c), ctypes.c_void_p(G.ptr), _ptr(params),
+                                   _ptr(ddelta), _ptr(dparams), ctypes.c_void_p(wp), wn,
+                                   _stream(stream)), "gnn_backward")
+    return dparams
+
+
+def gnn_factor_loss(G, M, delta, probes, grad=True, workspace=None, stream=None):
+    """(loss (device float64 scalar tensor), d loss / d delta or None, ws).
+    probes: float64 CUDA tensor (P, n)."""
+    A = G.A
+    P = probes.shape[0]
+    if probes.dtype != torch.float64 or probes.shape[1] != A.n or not probes.is_contiguous():
+        raise ValueError("probes must be a contiguous float64 (P, n) tensor")
+    nb = _lib().mpk_gnn_loss_workspace_bytes(ctypes.byref(A.c), P)
+    if workspace is None or workspace[2] < nb:
+        workspace = _workspace(nb, A.device)
+    _, wp, wn = workspace
+    loss = torch.empty((), dtype=torch.float64, device=A.device)
+    gd = torch.empty(A.nnz, dtype=torch.float32, device=A.device) if grad else None
+    _check(_lib().mpk_gnn_factor_loss(ctypes.byref(A.c), M.handle, ctypes.c_void_p(G.ptr),
+                                      _ptr(delta), P, _ptr(probes), _ptr(loss), _ptr(gd),
+                                      ctypes.c_void_p(wp), wn, _stream(stream)),
+           "gnn_factor_loss")
+    return loss, gd, workspace
+
+
+def gnn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """In-place Adam step on params (m, v: float32 state of the same size)."""
+    _check(_lib().mpk_gnn_adam(params.numel(), int(step), float(lr), float(beta1), float(beta2),
+                               float(eps), _ptr(params), _ptr(grad), _ptr(m), _ptr(v),
+                               _stream(stream)), "gnn_adam")
+
+
+def ilu0_correct(M, delta, stream=None):
+    """Apply the correction to M in place; returns True if the guards
+    rejected it (M unchanged)."""
+    fb = ctypes.c_int32(0)
+    _check(_lib().mpk_ilu0_correct(M.handle, _ptr(delta), ctypes.byref(fb), _stream(stream)),
+           "ilu0_correct")
+    return bool(fb.value)

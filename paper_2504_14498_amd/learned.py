@@ -7,8 +7,12 @@ orders the calls.  The paper has no learned part; the network and its
 loss are defined in include/mpk.h.
 
 Training data of one system: A, b, its plain ILU(0) factor and probe
-vectors, the normalised residuals r_k / ||r_k|| of the plain method at a
-few points of a restarted run (the method's own residual history).
+vectors: the normalised residuals r_k / ||r_k|| of the plain method at a
+few points of a restarted run (the method's own residual history), plus a
+few seeded Gaussian directions.  The residual probes pull the factor
+towards A on the slowly converging directions; the random ones keep it
+close to A everywhere else (without them the loss keeps falling while
+some systems stop converging).
 """
 import math
 import time
@@ -19,6 +23,7 @@ import torch
 from . import mpk
 
 PROBE_SEGMENTS = (4, 4, 8, 16)   # restarted plain BiCGSTAB passes between probes
+RANDOM_PROBES = 8                # plus this many seeded Gaussian directions
 
 
 def residual(A, b, x):
@@ -30,7 +35,8 @@ def residual(A, b, x):
 class Instance:
     """One system on the device with what training or solving needs."""
 
-    def __init__(self, problem, probes=True, segments=PROBE_SEGMENTS):
+    def __init__(self, problem, probes=True, segments=PROBE_SEGMENTS, nrandom=RANDOM_PROBES,
+                 seed=0):
         p = problem
         self.name = p.name
         self.A = mpk.Csr.from_problem(p)
@@ -38,7 +44,15 @@ class Instance:
         self.b = mpk.csr_spmv(self.A, xt)
         self.M = mpk.ilu0_factor(self.A, fprec=1, vprec=2)
         self.G = mpk.GnnGraph(self.A, self.M)
-        self.probes = self._probes(segments) if probes else None
+        self.probes = None
+        if probes:
+            P = self._probes(segments)
+            if nrandom:
+                R = np.random.Generator(np.random.PCG64(77_000_000 + seed)).standard_normal(
+                    (nrandom, self.A.n))
+                R /= np.linalg.norm(R, axis=1, keepdims=True)
+                P = torch.cat([P, torch.as_tensor(R, device=P.device)])
+            self.probes = P.contiguous()
 
     def _probes(self, segments):
         A, b = self.A, self.b
@@ -56,6 +70,8 @@ class Instance:
             rows.append(r / nr)
             if info["status"] == "ok":
                 break
+        if not rows:
+            return torch.zeros((0, A.n), dtype=torch.float64, device=b.device)
         return torch.stack(rows).contiguous()
 
 
@@ -139,8 +155,18 @@ def solve_learned(A, b, params, iter_cap, tol=1e-25, max_iter=10000):
 
 def iteration_cap(plain_iters, factor=1.5):
     """The learned solve's budget: factor x the plain method's count,
-    estimated from the training systems (their largest plain count)."""
+    estimated from systems of the training distribution (their largest
+    plain count)."""
     return int(math.ceil(factor * max(plain_iters)))
+
+
+def validation_ratio(params, systems, plain_iters, cap):
+    """Median over held-out training-distribution systems of learned /
+    plain iterations (fallbacks counted): the method itself judges which
+    parameters to keep."""
+    r = [solve_learned(A, b, params, cap)[1]["iters_total"] / max(pi, 1)
+         for (A, b), pi in zip(systems, plain_iters)]
+    return float(np.median(r))
 
 
 def quartiles(v):

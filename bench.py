@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run only SpMV, ILU(0) apply and a calibration copy (counter runs)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="convdiff3d",
                     choices=["convdiff3d", "batched", "learned"])
     ap.add_argument("--lgrid", type=int, default=512, help="grid of the learned workload")
@@ -310,6 +313,22 @@ def main():
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
     note("problem %s: n=%d nnz=%d" % (p.name, p.n, p.nnz))
+    if args.kernels_only:
+        # for hardware-counter runs: the two hot operations alone, plus a
+        # plain device copy of known size whose counters calibrate theirs
+        M = mpk.ilu0_factor(A, KF, vprec=K)
+        y = torch.empty_like(b)
+        z = torch.empty_like(b)
+        src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(args.reps):
+            mpk.csr_spmv(A, b, y)
+            mpk.ilu0_apply(M, b, z)
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        note("kernels only: %d x (spmv, ilu0 apply, copy of %d MiB)" % (args.reps, args.copy_mib))
+        return
     for _ in range(args.warmup):
         x, info = mpk.krylov_solve("bicgstab", A, b, fprec=KF, tol_rel=tol, max_iter=max_iter,
                                    workspace=ws, graph=bool(args.graph))

@@ -139,6 +139,17 @@ int validate_csr_args(const mpk_csr *A);
 int csr_check_device_values(const mpk_csr *A, int C, int32_t *word, int64_t *bad_row,
                             hipStream_t s);
 inline unsigned nblocks(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
+
+// Workgroups are dispatched to the 8 XCDs in turn.  Row kernels renumber
+// them so that each XCD walks one contiguous range of row blocks: rows that
+// share x values (stencil neighbours) then meet in the same L2.  The grid
+// is padded to a multiple of 8; padding blocks do nothing.
+constexpr unsigned NXCD = 8;
+inline unsigned xcd_grid(unsigned nb) { return (nb + NXCD - 1) / NXCD * NXCD; }
+__device__ __forceinline__ int64_t xcd_block() {
+  const unsigned b = blockIdx.x, per = gridDim.x / NXCD;
+  return int64_t(b % NXCD) * per + b / NXCD;
+}
 double now_ms();
 
 // Launch error check for host code.

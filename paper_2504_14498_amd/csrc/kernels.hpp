@@ -82,17 +82,20 @@ __device__ __forceinline__ el<C, K> row_spmv(int64_t i, const int32_t *__restric
 }
 
 // Generic row/element kernel: op(i, dots) for i < n; optional ND fused
-// inner-product partials written per workgroup.  Skipped when *done.
+// inner-product partials written per row block.  Skipped when *done.
+// Launch with xcd_grid(nblocks(n)) workgroups.
 template <int C, int K, int ND, class Op>
 __global__ __launch_bounds__(BLOCK) void row_kernel(int64_t n, Op op, const int32_t *done,
                                                     double *partials) {
   if (done && *done) return;
-  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  const int64_t lb = xcd_block();
+  if (lb * BLOCK >= n) return;
+  const int64_t i = lb * BLOCK + threadIdx.x;
   el<C, K> d[ND > 0 ? ND : 1];
 #pragma unroll
   for (int q = 0; q < (ND > 0 ? ND : 1); ++q) d[q] = el_zero<C, K>();
   if (i < n) op(i, d);
-  if constexpr (ND > 0) block_reduce<C, K, ND>(d, partials + size_t(blockIdx.x) * ND * C * K);
+  if constexpr (ND > 0) block_reduce<C, K, ND>(d, partials + size_t(lb) * ND * C * K);
 }
 
 template <int C, int K> struct SpmvOp {

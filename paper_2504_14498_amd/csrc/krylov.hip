@@ -55,12 +55,14 @@ template <int C, int K, int ND, class Op>
 __global__ __launch_bounds__(BLOCK) void srow_kernel(int64_t n, Op op, const KState *st, int gate,
                                                      double *partials) {
   if (st->done || (gate >= 0 && st->phase != gate)) return;
-  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  const int64_t lb = xcd_block();
+  if (lb * BLOCK >= n) return;
+  const int64_t i = lb * BLOCK + threadIdx.x;
   el<C, K> d[ND > 0 ? ND : 1];
 #pragma unroll
   for (int q = 0; q < (ND > 0 ? ND : 1); ++q) d[q] = el_zero<C, K>();
   if (i < n) op(i, st, d);
-  if constexpr (ND > 0) block_reduce<C, K, ND>(d, partials + size_t(blockIdx.x) * ND * C * K);
+  if constexpr (ND > 0) block_reduce<C, K, ND>(d, partials + size_t(lb) * ND * C * K);
 }
 
 // ------------------------------------------------------- shared ops
@@ -581,7 +583,7 @@ template <int C, int K> struct Solver {
   int nblk;
 
   template <int ND, class Op> void rows(Op op, int gate = GATE_ANY) {
-    hipLaunchKernelGGL((srow_kernel<C, K, ND, Op>), dim3(nblk), dim3(BLOCK), 0, s, n, op,
+    hipLaunchKernelGGL((srow_kernel<C, K, ND, Op>), dim3(xcd_grid(nblk)), dim3(BLOCK), 0, s, n, op,
                        (const KState *)L.st, gate, L.partials);
   }
   void scalar(int mode) {

@@ -43,7 +43,7 @@ int spmv_launch(int C, int K, int64_t n, const int32_t *rp, const int32_t *ci, c
   if (n == 0) return MPK_OK;
   return dispatch_ck(C, K, [&]<int CC, int KK>() {
     SpmvOp<CC, KK> op{rp, ci, val, x, y};
-    hipLaunchKernelGGL((row_kernel<CC, KK, 0, SpmvOp<CC, KK>>), dim3(nblocks(n)), dim3(BLOCK), 0,
+    hipLaunchKernelGGL((row_kernel<CC, KK, 0, SpmvOp<CC, KK>>), dim3(xcd_grid(nblocks(n))), dim3(BLOCK), 0,
                        s, n, op, done, (double *)nullptr);
     return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
   });
@@ -495,7 +495,7 @@ int mpk_dot(mpk_prec p, int is_complex, int64_t n, const double *a, const double
   const int nb = int(nblocks(n));
   return dispatch_ck(is_complex ? 2 : 1, int(p), [&]<int C, int K>() {
     DotOp<C, K> op{a, b};
-    hipLaunchKernelGGL((row_kernel<C, K, 1, DotOp<C, K>>), dim3(nb), dim3(BLOCK), 0, s, n, op,
+    hipLaunchKernelGGL((row_kernel<C, K, 1, DotOp<C, K>>), dim3(xcd_grid(nb)), dim3(BLOCK), 0, s, n, op,
                        (const int32_t *)nullptr, part);
     hipLaunchKernelGGL((dot_final<C, K>), dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
                        out);

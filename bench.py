@@ -203,19 +203,41 @@ def bench_learned(args):
     best = (1.0, tr.params.clone(), 0)     # delta = 0 is the plain factor
     losses = []
     t_train = time.perf_counter()
-    for k, p in enumerate(pool.map(gen, range(ntrain - nval))):
+    ntr = ntrain - nval if not args.load_params else 0
+    for k, p in enumerate(pool.map(gen, range(ntr))):
         inst = LR.Instance(p, seed=k)
         losses.append(float(tr.step(inst)))
         del inst
-        if (k + 1) % args.val_every == 0 or k + 1 == ntrain - nval:
+        if (k + 1) % 50 == 0:
+            note("step %d: mean loss of the last 50 %.4e" % (k + 1, np.mean(losses[-50:])))
+        if (k + 1) % args.val_every == 0 or k + 1 == ntr:
             r = LR.validation_ratio(tr.params, val, val_plain, cap)
             if r < best[0]:
                 best = (r, tr.params.clone(), k + 1)
-            note("step %d: mean loss %.4e, validation iteration ratio %.3f (best %.3f at %d)"
-                 % (k + 1, np.mean(losses[-args.val_every:]), r, best[0], best[2]))
+            note("step %d: validation iteration ratio %.3f (best %.3f at %d)"
+                 % (k + 1, r, best[0], best[2]))
     train_s = time.perf_counter() - t_train
     params = best[1]
+    train_info = {"seconds": train_s, "steps": len(losses), "lr": args.lr, "kept_step": best[2],
+                  "validation_ratio": best[0],
+                  "loss_first_100": float(np.mean(losses[:100])) if losses else None,
+                  "loss_last_100": float(np.mean(losses[-100:])) if losses else None}
+    if args.load_params:
+        saved = np.load(args.load_params, allow_pickle=False)
+        params = torch.as_tensor(saved["params"]).cuda()
+        train_info = json.loads(str(saved["train_info"]))
+        note("loaded parameters from %s (trained %d steps)" % (args.load_params,
+                                                               train_info["steps"]))
+    if args.save_params:
+        np.savez(args.save_params, params=params.cpu().numpy(),
+                 train_info=np.array(json.dumps(train_info)))
+        note("saved parameters to %s" % args.save_params)
     rows = []
+    if ntest == 0:
+        pool.shutdown()
+        print(json.dumps({"training": train_info, "validation_plain_iters": val_plain,
+                          "cap": cap}))
+        return
     for q, p in enumerate(pool.map(gen, range(100_000, 100_000 + ntest))):
         A = LR.mpk.Csr.from_problem(p)
         b = LR.mpk.csr_spmv(A, torch.as_tensor(p.x_true_limbs(2)).cuda())
@@ -247,10 +269,7 @@ def bench_learned(args):
            "median_ratio": {"tts": float(np.median(r[:, 3] / r[:, 1])),
                             "iters": float(np.median(r[:, 2] / r[:, 0]))},
            "both_converged": ok, "max_learned_relres_true": max(row[7] for row in rows),
-           "training": {"seconds": train_s, "steps": len(losses), "lr": args.lr,
-                        "kept_step": best[2], "validation_ratio": best[0],
-                        "loss_first_100": float(np.mean(losses[:100])),
-                        "loss_last_100": float(np.mean(losses[-100:]))},
+           "training": train_info,
            "total_s": time.perf_counter() - t0}
     print(json.dumps(out))
 
@@ -277,6 +296,8 @@ def main():
     ap.add_argument("--val-every", type=int, default=250)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--save-params", default=None, help="learned workload: save the kept parameters (.npz)")
+    ap.add_argument("--load-params", default=None, help="learned workload: skip training, load (.npz)")
     ap.add_argument("--nsys", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=8)
     args = ap.parse_args()

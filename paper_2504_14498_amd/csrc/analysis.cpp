@@ -132,6 +132,7 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
   }
   p.mode = (total > 0 && 2 * internal >= total) ? 1 : 0;
   if (const char *e = getenv("MPK_TRSV_MODE")) p.mode = (e[0] == 'b') ? 1 : (e[0] == 'l' ? 0 : p.mode);
+  if (blk_rows <= 0) p.mode = 0;  // blocked schedule not available
   p.nlev = nlev;
   auto counting_order = [&](std::vector<int32_t> &levptr, std::vector<int32_t> &order) {
     levptr.assign(size_t(nlev) + 1, 0);
@@ -183,7 +184,10 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
     cnt.assign(size_t(nl) + 1, 0);
     for (int64_t i = r0; i < r1; ++i) cnt[loc[i - r0] + 1]++;
     for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
-    for (int32_t l = 0; l < nl; ++l) p.loc_pos.push_back(base + cnt[l]);
+    // a local level wider than a workgroup is cut into pieces of at most
+    // BLOCK rows (its rows are independent), so a lane owns one row
+    for (int32_t l = 0; l < nl; ++l)
+      for (int32_t q = cnt[l]; q < cnt[l + 1]; q += BLOCK) p.loc_pos.push_back(base + q);
     for (int64_t i = r0; i < r1; ++i) p.order[base + cnt[loc[i - r0]]++] = int32_t(i);
     base += int32_t(r1 - r0);
   }

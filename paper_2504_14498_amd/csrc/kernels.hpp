@@ -62,21 +62,49 @@ __device__ __forceinline__ void reduce_partials(const double *partials, int nblk
 }
 
 // ------------------------------------------------------------------ SpMV
+// Entries of a row whose loads are issued together.
+template <int C, int K> constexpr int spmv_batch() { return C * K <= 2 ? 8 : 4; }
+
 // Row i of y = A x: products in ascending column order, accumulated in
 // the working precision starting from the first product (empty row: 0).
+// The first spmv_batch entries' indices, values and x words are requested
+// together (indices clamped into the row; the extra words are not used),
+// so a short stencil row costs two memory round trips instead of two per
+// entry; longer rows continue one entry at a time.
 template <int C, int K>
 __device__ __forceinline__ el<C, K> row_spmv(int64_t i, const int32_t *__restrict__ rp,
                                              const int32_t *__restrict__ ci,
                                              const double *__restrict__ val,
                                              const double *__restrict__ x) {
+  constexpr int U = spmv_batch<C, K>();
   const int32_t a = rp[i], b = rp[i + 1];
   el<C, K> acc = el_zero<C, K>();
-  for (int32_t p = a; p < b; ++p) {
-    double f[C];
+  if (b > a) {
+    int32_t cj[U];
+    double f[U][C];
+    el<C, K> xv[U];
 #pragma unroll
-    for (int c = 0; c < C; ++c) f[c] = val[size_t(p) * C + c];
-    el<C, K> t = el_mul_f<C, K, 1>(f, el_load<C, K>(x + size_t(ci[p]) * C * K));
-    acc = (p == a) ? t : el_add<C, K>(acc, t);
+    for (int u = 0; u < U; ++u) {
+      const int32_t p = min(a + u, b - 1);
+      cj[u] = ci[p];
+#pragma unroll
+      for (int c = 0; c < C; ++c) f[u][c] = val[size_t(p) * C + c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = el_load<C, K>(x + size_t(cj[u]) * C * K);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (a + u < b) {
+        const el<C, K> t = el_mul_f<C, K, 1>(f[u], xv[u]);
+        acc = u == 0 ? t : el_add<C, K>(acc, t);
+      }
+    }
+    for (int32_t p = a + U; p < b; ++p) {
+      double fp[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) fp[c] = val[size_t(p) * C + c];
+      acc = el_add<C, K>(acc, el_mul_f<C, K, 1>(fp, el_load<C, K>(x + size_t(ci[p]) * C * K)));
+    }
   }
   return acc;
 }
@@ -501,97 +529,151 @@ __global__ __launch_bounds__(BLOCK) void trsv_syncfree(
 // software-pipelined: while level l is computed from LDS, the row data,
 // factor values and external y values of level l+1 are already in flight.
 // Row arithmetic is identical to the level schedule's.
-template <int C, int K, int KF, int MAXD> struct RowPre {
-  int32_t i, pos, pb, pe;
-  bool valid;
-  el<C, K> acc;
-  int32_t cj[MAXD];
-  double f[MAXD][C * KF];
-  el<C, K> ye[MAXD];
-  bool ok;
-};
+// ---- blocked sweep ------------------------------------------------------
+// Every memory access of a level is one buffer instruction issued by all
+// lanes whatever their row: a lane without a row (or a dependency slot
+// that is not external) uses an offset past the buffer's end, which the
+// hardware turns into a zero load or a dropped store without touching
+// memory.  With no memory operation under a lane- or level-dependent
+// branch, the compiler counts the loads in flight and waits only for the
+// ones a level needs, so the next levels' row data and external values
+// stay in flight across the level barriers; loaded words are first used
+// when their level is finished.
 
-// Stage 1 (several levels ahead): the row index, its dependency count,
-// the first ELLW dependency columns and their factor values -- all indexed
-// by the position, so one memory round trip covers the stage.
-template <int C, int K, int KF, bool CONJ, int MAXD>
-__device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_t pos, bool valid,
-                                               const int32_t *__restrict__ order,
-                                               const int32_t *__restrict__ ell_nd,
-                                               const int32_t *__restrict__ ell_col,
-                                               const double *__restrict__ ell_val) {
-  r.pos = pos;
-  r.valid = valid;
-  r.ok = true;
-  if (!valid) {
-    r.pb = r.pe = 0;
-    return;
-  }
-  r.i = order[pos];
-  r.pb = 0;
-  r.pe = ell_nd[pos];
-#pragma unroll
-  for (int d = 0; d < MAXD; ++d) {
-    r.cj[d] = ell_col[size_t(pos) * ELLW + d];
-    load_f<C, KF, CONJ>(ell_val + (size_t(pos) * ELLW + d) * C * KF, r.f[d]);
-  }
+typedef unsigned int bu2 __attribute__((ext_vector_type(2)));
+typedef unsigned int bu4 __attribute__((ext_vector_type(4)));
+constexpr int BUF_AGENT = 16;               // cache policy: coherent at agent scope (sc1)
+constexpr uint32_t BUF_OOB = 0xFFFFFF00u;   // an offset past every buffer's end
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, int(bytes),
+                                           0x00020000);
+}
+template <int AUX>
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, AUX));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), r, int(off), 0, BUF_AGENT);
 }
 
-// Stage 2 (one level ahead): the y values of dependencies outside the block.
-template <int C, int K, int KF, int MAXD>
-__device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const double *out,
-                                              int32_t r0, int32_t r1) {
-  constexpr int E = C * K;
-  r.ok = true;
-  if (!r.valid) return;
+template <int C, int K, int KF, int MAXD> struct RowPre {
+  int32_t i, pos, nd;
+  bool valid;
+  int32_t cj[MAXD];
+  double f[MAXD][C * KF];
+  double dv[C * KF];   // pivot (backward sweeps)
+  el<C, K> ye[MAXD];   // words of external dependencies (raw)
+};
+
+// The buffers of one sweep.
+struct SweepBufs {
+  __amdgpu_buffer_rsrc_t order, nd, col, val, dval, out;
+};
+
+// Stage 1 (D levels ahead): row index, dependency count, the first ELLW
+// dependency columns and factor values, and the pivot, by position.
+template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
+__device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_t pos, bool valid,
+                                               const SweepBufs &B) {
+  static_assert(MAXD == ELLW, "one slot per flat dependency");
+  r.pos = pos;
+  r.valid = valid;
+  const uint32_t p4 = valid ? uint32_t(pos) * 4u : BUF_OOB;
+  r.i = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.order, int(p4), 0, 0));
+  r.nd = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.nd, int(p4), 0, 0));
+  const bu4 cj = __builtin_amdgcn_raw_buffer_load_b128(
+      B.col, int(valid ? uint32_t(pos) * 4u * ELLW : BUF_OOB), 0, 0);
+  r.cj[0] = int32_t(cj.x);
+  r.cj[1] = int32_t(cj.y);
+  r.cj[2] = int32_t(cj.z);
+  r.cj[3] = int32_t(cj.w);
+  const uint32_t fo = valid ? uint32_t(pos) * uint32_t(ELLW * C * KF * 8) : BUF_OOB;
 #pragma unroll
-  for (int d = 0; d < MAXD; ++d) {
-    if (d < r.pe && !(r.cj[d] >= r0 && r.cj[d] < r1)) {
-      const double *yp = out + size_t(r.cj[d]) * E;
+  for (int d = 0; d < MAXD; ++d)
 #pragma unroll
-      for (int c = 0; c < C; ++c)
+    for (int v = 0; v < C * KF; ++v) {
+      const double x = buf_ld<0>(B.val, fo + uint32_t((d * C * KF + v) * 8));
+      r.f[d][v] = (CONJ && v >= KF) ? -x : x;
+    }
+  if constexpr (DIV) {
+    const uint32_t dofs = valid ? uint32_t(pos) * uint32_t(C * KF * 8) : BUF_OOB;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          uint64_t bits = ld_agent(yp + c * K + k);
-          r.ok = r.ok && (bits != SENTINEL);
-          r.ye[d].c[c].v[k] = __builtin_bit_cast(double, bits);
-        }
+    for (int v = 0; v < C * KF; ++v) {
+      const double x = buf_ld<0>(B.dval, dofs + uint32_t(v * 8));
+      r.dv[v] = (CONJ && v >= KF) ? -x : x;
     }
   }
 }
 
+template <int C, int K, int KF, int MAXD>
+__device__ __forceinline__ bool dep_external(const RowPre<C, K, KF, MAXD> &r, int d, int32_t r0,
+                                             int32_t r1) {
+  return r.valid && d < r.nd && !(r.cj[d] >= r0 && r.cj[d] < r1);
+}
+
+// Stage 2 (X levels ahead): the words of dependencies outside the block.
+template <int C, int K, int KF, int MAXD>
+__device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const SweepBufs &B,
+                                              int32_t r0, int32_t r1) {
+  constexpr int E = C * K;
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) {
+    const uint32_t o = dep_external<C, K, KF, MAXD>(r, d, r0, r1)
+                           ? uint32_t(r.cj[d]) * uint32_t(E * 8) : BUF_OOB;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        r.ye[d].c[c].v[k] = buf_ld<BUF_AGENT>(B.out, o + uint32_t((c * K + k) * 8));
+  }
+}
+
+// Finish one row: acc = rhs_i (staged in the row's LDS slot) minus the
+// products in ascending column order, divided by the pivot when DIV; the
+// result goes to the row's LDS slot and to out.  A lane without a row uses
+// LDS slot r1 - r0 and an out-of-range store.
 template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
 __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int32_t *__restrict__ ptr,
                                            const int32_t *__restrict__ col,
-                                           const double *__restrict__ val,
-                                           const double *__restrict__ dval, double *out, double *lds,
-                                           int32_t r0, int32_t r1, int32_t *abort_flag) {
+                                           const double *__restrict__ val, double *out,
+                                           const SweepBufs &B, double *lds, int32_t r0,
+                                           int32_t r1, int32_t *abort_flag) {
   constexpr int E = C * K;
-  // the block's rhs was staged into LDS; the slot of row i holds rhs_i until
-  // y_i replaces it
-  el<C, K> acc = el_load<C, K>(lds + size_t(r.i - r0) * E);
+  const int32_t pe = r.valid ? r.nd : 0;
+  const int32_t slot = r.valid ? r.i - r0 : r1 - r0;
+  el<C, K> acc = el_load<C, K>(lds + size_t(slot) * E);
   {
     el<C, K> yv[MAXD];
+    bool ok = true;
 #pragma unroll
     for (int d = 0; d < MAXD; ++d) {
-      if (d < r.pe) {
-        const int32_t j = r.cj[d];
-        if (j >= r0 && j < r1) {
-          yv[d] = el_load<C, K>(lds + size_t(j - r0) * E);
-        } else {
-          yv[d] = r.ye[d];
-          if (!r.ok) wait_load<C, K>(out + size_t(j) * E, yv[d], abort_flag);
-        }
+      const int32_t j = r.cj[d];
+      const bool in = j >= r0 && j < r1;
+      yv[d] = el_load<C, K>(lds + size_t(d < pe && in ? j - r0 : r1 - r0) * E);
+      if (d < pe && !in) {
+        yv[d] = r.ye[d];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            ok = ok && __builtin_bit_cast(uint64_t, yv[d].c[c].v[k]) != SENTINEL;
       }
+    }
+    if (!ok) {
+#pragma unroll
+      for (int d = 0; d < MAXD; ++d)
+        if (dep_external<C, K, KF, MAXD>(r, d, r0, r1))
+          wait_load<C, K>(out + size_t(r.cj[d]) * E, yv[d], abort_flag);
     }
 #pragma unroll
     for (int d = 0; d < MAXD; ++d)
-      if (d < r.pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
+      if (d < pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
   }
   // rows with more than MAXD dependencies: the rest from the CSR arrays
-  if (r.pe > MAXD) {
+  if (pe > MAXD) {
     const int32_t pb = ptr[r.pos];
-    for (int32_t d = MAXD; d < r.pe; ++d) {
+    for (int32_t d = MAXD; d < pe; ++d) {
       const int32_t j = col[pb + d];
       el<C, K> yj;
       if (j >= r0 && j < r1)
@@ -603,19 +685,16 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
       acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, yj));
     }
   }
-  if constexpr (DIV) {
-    double d[C * KF];
-    load_f<C, KF, CONJ>(dval + size_t(r.pos) * C * KF, d);
-    acc = el_div_k<C, K, KF>(acc, d);
-  }
+  if constexpr (DIV) acc = el_div_k<C, K, KF>(acc, r.dv);
+  const uint32_t oo = r.valid ? uint32_t(r.i) * uint32_t(E * 8) : BUF_OOB;
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double v = acc.c[c].v[k];
       v = v != v ? __builtin_nan("") : v;
-      lds[size_t(r.i - r0) * E + c * K + k] = v;
-      st_agent(out + size_t(r.i) * E + c * K + k, v);
+      lds[size_t(slot) * E + c * K + k] = v;
+      buf_st(B.out, oo + uint32_t((c * K + k) * 8), v);
     }
 }
 
@@ -631,11 +710,18 @@ __device__ __forceinline__ void lds_barrier() {
 // Prefetch depth (local levels) of the blocked sweep's row data.
 template <int E> constexpr int trsv_depth() { return E <= 2 ? 4 : 2; }
 
-// About one workgroup per CU (the LDS block decides), so the register
-// budget may grow to keep the prefetch stages out of scratch.
+// Blocked sweep: a workgroup takes the next block of consecutive rows (in
+// sweep order), stages its rhs in LDS and walks the block's local levels
+// (each at most BLOCK rows: one per lane), separated by LDS-only barriers.
+// Values of other blocks are read from out with the sentinel-checked
+// wait.  LDS: (rows per block + 1) * C * K doubles, the last slot for
+// lanes without a row.  The buffers' byte sizes must stay below 2^31
+// (the host picks the level schedule otherwise).  About one workgroup per
+// CU (the LDS block decides), so the register budget may grow to keep the
+// prefetch stages out of scratch.
 template <int C, int K, int KF, bool DIV, bool CONJ>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_blocked(
-    const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
+    int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
     const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
@@ -648,8 +734,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   constexpr int E = C * K;
   constexpr int MAXD = ELLW;
   constexpr int D = trsv_depth<E>();
+  constexpr int X = D - 1;  // levels ahead at which external values are requested
   using RP = RowPre<C, K, KF, MAXD>;
   const int32_t tid = threadIdx.x;
+  SweepBufs B;
+  B.order = buf_rsrc(order, n * 4);
+  B.nd = buf_rsrc(ell_nd, n * 4);
+  B.col = buf_rsrc(ell_col, n * 4 * ELLW);
+  B.val = buf_rsrc(ell_val, n * ELLW * C * KF * 8);
+  B.dval = buf_rsrc(DIV ? dval : ell_val, DIV ? n * C * KF * 8 : 0);
+  B.out = buf_rsrc(out, n * E * 8);
   for (;;) {
     if (tid == 0) cur = atomicAdd(ticket, 1);
     __syncthreads();
@@ -660,58 +754,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     const int32_t l0 = blk_lev[b], l1 = blk_lev[b + 1];
     // stage the block's right-hand side into LDS (contiguous rows)
     for (int64_t w = tid; w < int64_t(r1 - r0) * E; w += BLOCK) lds[w] = rhs[size_t(r0) * E + w];
+    // row data of local level l (empty past the block's last level)
+    auto meta = [&](RP &r, int32_t l) {
+      const int32_t pb = loc_pos[min(l, l1)], pe = loc_pos[min(l + 1, l1)];
+      row_fetch_meta<C, K, KF, DIV, CONJ, MAXD>(r, pb + tid, pb + tid < pe, B);
+    };
     RP st[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int32_t l = l0 + u;
-      if (l < l1) {
-        const int32_t pos = loc_pos[l] + tid;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(st[u], pos, pos < loc_pos[l + 1], order, ell_nd,
-                                             ell_col, ell_val);
-      } else {
-        st[u].valid = false;
-      }
-    }
+    for (int u = 0; u < D; ++u) meta(st[u], l0 + u);
     __syncthreads();
-    // external values of the first D-1 levels (their column indices are in)
 #pragma unroll
-    for (int u = 0; u + 1 < D; ++u) row_fetch_ext<C, K, KF, MAXD>(st[u], out, r0, r1);
+    for (int u = 0; u < X; ++u) row_fetch_ext<C, K, KF, MAXD>(st[u], B, r0, r1);
     // one local level: finish `now`; then request the external values of
-    // level l+D-1 (slot `ext`, whose indices arrived one stage ago) and
+    // level l+X (slot `ext`, whose indices arrived D-X stages ago) and
     // refill `now` with the row data of level l+D
     auto stage = [&](RP &now, RP &ext, int32_t l) {
-      const int32_t pbeg = loc_pos[l], pend = loc_pos[l + 1];
-      if (now.valid)
-        row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, dval, out, lds, r0, r1,
-                                              abort_flag);
-      for (int32_t pos = pbeg + BLOCK + tid; pos < pend; pos += BLOCK) {
-        RP x;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(x, pos, true, order, ell_nd, ell_col, ell_val);
-        row_fetch_ext<C, K, KF, MAXD>(x, out, r0, r1);
-        row_finish<C, K, KF, DIV, CONJ, MAXD>(x, ptr, col, val, dval, out, lds, r0, r1,
-                                              abort_flag);
-      }
+      row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, out, B, lds, r0, r1,
+                                            abort_flag);
       lds_barrier();
-      if (l + D - 1 < l1) row_fetch_ext<C, K, KF, MAXD>(ext, out, r0, r1);
-      if (l + D < l1) {
-        const int32_t pos = loc_pos[l + D] + tid;
-        row_fetch_meta<C, K, KF, CONJ, MAXD>(now, pos, pos < loc_pos[l + D + 1], order, ell_nd,
-                                             ell_col, ell_val);
-      } else {
-        now.valid = false;
-      }
+      row_fetch_ext<C, K, KF, MAXD>(ext, B, r0, r1);
+      meta(now, l + D);
     };
     for (int32_t lv = l0; lv < l1; lv += D) {
-      if constexpr (D == 4) {
-        stage(st[0], st[3], lv);
-        if (lv + 1 < l1) stage(st[1], st[0], lv + 1);
-        if (lv + 2 < l1) stage(st[2], st[1], lv + 2);
-        if (lv + 3 < l1) stage(st[3], st[2], lv + 3);
-      } else {
-        stage(st[0], st[1], lv);
-        if (lv + 1 < l1) stage(st[1], st[0], lv + 1);
-      }
+#pragma unroll
+      for (int u = 0; u < D; ++u) stage(st[u], st[(u + X) % D], lv + u);
     }
+    __syncthreads();
   }
 }
 

@@ -183,7 +183,9 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   hipLaunchKernelGGL(find_diag, dim3(nblocks(A->n)), dim3(BLOCK), 0, s, A->n, A->row_ptr,
                      A->col_idx, M->diag);
   const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
-  const int br = default_block_rows(C, kmax);
+  // the blocked sweeps address their arrays with 32-bit buffer offsets
+  const int64_t big = int64_t(A->n) * std::max(ELLW * C * KF, C * kmax) * 8;
+  const int br = big < (int64_t(1) << 31) ? default_block_rows(C, kmax) : 0;
   HostPlan hp[4];
   HostCsr ht;
   const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
@@ -271,9 +273,9 @@ static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
       return e ? std::max<int64_t>(1, atoll(e)) : int64_t(512);
     }();
     const unsigned grid = unsigned(std::min<int64_t>(P.nblk, bcap));
-    const size_t lds = size_t(P.blk_rows) * C * K * sizeof(double);
+    const size_t lds = size_t(P.blk_rows + 1) * C * K * sizeof(double);
     hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK),
-                       lds, s, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
+                       lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
                        P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_val, rhs, out, P.sync,
                        abort_flag, done);
     return;

@@ -72,6 +72,27 @@ def test_spmv_bitwise(mpk, orc, name, K):
     assert np.array_equal(y, yo)
 
 
+@pytest.mark.parametrize("C", [1, 2])
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_spmv_ragged_rows_bitwise(mpk, orc, C, K):
+    """Empty rows, rows shorter and longer than the batch of entries whose
+    loads are issued together, and a last row that is empty."""
+    rng = np.random.default_rng(31 + K)
+    n = 1300
+    lens = rng.choice([0, 1, 3, 7, 8, 9, 17, 40], size=n)
+    lens[-1] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n, size=l, replace=False)) for l in lens if l > 0]
+                        ).astype(np.int32)
+    val = rng.standard_normal((len(ci), C)) if C == 2 else rng.standard_normal(len(ci))
+    A = mpk.Csr(rp, ci, val)
+    x = rand_vec(np.random.default_rng(K), n, C, K)
+    y = host(mpk.csr_spmv(A, dev(x)))
+    yo = orc.spmv(rp, ci, val, x)
+    assert np.array_equal(y, yo)
+    assert np.all(y[lens == 0] == 0)
+
+
 @pytest.mark.parametrize("name", ["rand_real", "rand_cplx"])
 @pytest.mark.parametrize("K", [2, 4])
 def test_spmv_transpose_bitwise(mpk, orc, name, K):

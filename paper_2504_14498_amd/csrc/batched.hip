@@ -102,10 +102,9 @@ __device__ void blevels(const BSys &S, bool lower, int32_t *ord, int32_t *lpt, i
       }
     }
     tl[tid] = ext;
+    if (tid == 0) changed = 0;
     __syncthreads();
     for (;;) {
-      if (tid == 0) changed = 0;
-      __syncthreads();
       int32_t l = ext;
       if (valid) {
         for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
@@ -115,13 +114,16 @@ __device__ void blevels(const BSys &S, bool lower, int32_t *ord, int32_t *lpt, i
           if (dep && tj >= c) l = max(l, tl[tj - c] + 1);
         }
       }
-      __syncthreads();
+      __syncthreads();  // every read of tl in this round is done
       if (valid && l != tl[tid]) {
         tl[tid] = l;
         changed = 1;
       }
-      __syncthreads();
-      if (!changed) break;
+      __syncthreads();  // the round's updates and flag are visible
+      const bool again = changed != 0;
+      __syncthreads();  // every thread has read the flag ...
+      if (tid == 0) changed = 0;  // ... before it is cleared for the next round
+      if (!again) break;
     }
     if (valid) {
       S.lvl[i] = tl[tid];
@@ -179,8 +181,39 @@ __device__ void bfactor(const BSys &S, int32_t nlev, int32_t *bad) {
   }
 }
 
+// acc - sum over p in [p0, p1) of f_p v_{ci[p]}, subtracted in ascending p.
+// Entries are taken eight at a time: their indices, factor values and
+// vector words are requested together (indices clamped into the range;
+// the extra words are not used), so a row costs two memory round trips per
+// eight entries instead of two per entry.
+template <int K, int KF>
+__device__ __forceinline__ el<1, K> bsub_products(el<1, K> acc, int32_t p0, int32_t p1,
+                                                  const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ f, const double *v) {
+  constexpr int U = 8;
+  for (int32_t pb = p0; pb < p1; pb += U) {
+    int32_t cj[U];
+    double fv[U][KF];
+    el<1, K> yv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t p = min(pb + u, p1 - 1);
+      cj[u] = ci[p];
+#pragma unroll
+      for (int q = 0; q < KF; ++q) fv[u][q] = f[size_t(p) * KF + q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) yv[u] = el_load<1, K>(v + size_t(cj[u]) * K);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (pb + u < p1) acc = el_sub<1, K>(acc, el_mul_f<1, K, KF>(fv[u], yv[u]));
+  }
+  return acc;
+}
+
 // z = (L U)^{-1} r with the level orders; y (intermediate) and z are
-// vectors of the system.  Row arithmetic as Algorithm 2.
+// vectors of the system.  Row arithmetic as Algorithm 2: the strict lower
+// part of row i is [rp_i, diag_i), the strict upper part (diag_i, rp_i+1).
 template <int K, int KF>
 __device__ void bapply(const BSys &S, const BShared<K> &sh, const double *r, double *y, double *z) {
   const int tid = threadIdx.x;
@@ -188,9 +221,7 @@ __device__ void bapply(const BSys &S, const BShared<K> &sh, const double *r, dou
     for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK) {
       const int32_t i = S.ordL[pos];
       el<1, K> acc = el_load<1, K>(r + size_t(i) * K);
-      for (int32_t p = S.rp[i]; p < S.rp[i + 1] && S.ci[p] < i; ++p)
-        acc = el_sub<1, K>(acc, el_mul_f<1, K, KF>(S.f + size_t(p) * KF,
-                                                   el_load<1, K>(y + size_t(S.ci[p]) * K)));
+      acc = bsub_products<K, KF>(acc, S.rp[i], S.diag[i], S.ci, S.f, y);
       el_store<1, K>(y + size_t(i) * K, acc);
     }
     __syncthreads();
@@ -199,9 +230,7 @@ __device__ void bapply(const BSys &S, const BShared<K> &sh, const double *r, dou
     for (int32_t pos = S.lptU[l] + tid; pos < S.lptU[l + 1]; pos += BLOCK) {
       const int32_t i = S.ordU[pos];
       el<1, K> acc = el_load<1, K>(y + size_t(i) * K);
-      for (int32_t p = S.diag[i] + 1; p < S.rp[i + 1]; ++p)
-        acc = el_sub<1, K>(acc, el_mul_f<1, K, KF>(S.f + size_t(p) * KF,
-                                                   el_load<1, K>(z + size_t(S.ci[p]) * K)));
+      acc = bsub_products<K, KF>(acc, S.diag[i] + 1, S.rp[i + 1], S.ci, S.f, z);
       acc = el_div_k<1, K, KF>(acc, S.f + size_t(S.diag[i]) * KF);
       el_store<1, K>(z + size_t(i) * K, acc);
     }

@@ -147,8 +147,88 @@ __device__ void blevels(const BSys &S, bool lower, int32_t *ord, int32_t *lpt, i
   *nlev_out = nlev;
 }
 
+// Row i of the factorisation (Algorithm 1, IKJ): for each k < i stored in
+// row i (ascending), l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for every
+// stored j > k of row k that row i also stores.  Rows of at most RCACHE
+// entries keep their column indices in the thread's LDS slice, so the
+// search for j is an LDS walk; row k's upper part is read eight entries at
+// a time and the matched a_ij are loaded together.  Longer rows take the
+// entry-by-entry path.  Both perform the same operations in the same order.
+constexpr int RCACHE = 32;
+
+template <int KF>
+__device__ __forceinline__ void bfactor_row(const BSys &S, int32_t i, int32_t *lc,
+                                            int32_t *bad) {
+  const int32_t a = S.rp[i], e = S.rp[i + 1], di = S.diag[i];
+  if (e - a <= RCACHE) {
+    for (int32_t b0 = a; b0 < e; b0 += 8) {
+      int32_t cb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cb[u] = S.ci[min(b0 + u, e - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < e) lc[b0 + u - a] = cb[u];
+    }
+    for (int32_t p = a; p < di; ++p) {
+      const int32_t k = lc[p - a];
+      const int32_t dk = S.diag[k], q1 = S.rp[k + 1];
+      el<1, KF> lik = el_load<1, KF>(S.f + size_t(p) * KF);
+      lik = el_div_k<1, KF, KF>(lik, S.f + size_t(dk) * KF);
+      el_store<1, KF>(S.f + size_t(p) * KF, lik);
+      int32_t r = p + 1 - a;  // walk position in row i
+      for (int32_t qb = dk + 1; qb < q1; qb += 8) {
+        int32_t cq[8], rm[8];
+        double fk[8][KF];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int32_t q = min(qb + u, q1 - 1);
+          cq[u] = S.ci[q];
+#pragma unroll
+          for (int v = 0; v < KF; ++v) fk[u][v] = S.f[size_t(q) * KF + v];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          rm[u] = -1;
+          if (qb + u < q1) {
+            while (r < e - a && lc[r] < cq[u]) ++r;
+            if (r < e - a && lc[r] == cq[u]) rm[u] = r;
+          }
+        }
+        el<1, KF> aij[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          aij[u] = el_load<1, KF>(S.f + size_t(a + (rm[u] >= 0 ? rm[u] : 0)) * KF);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (rm[u] >= 0)
+            el_store<1, KF>(S.f + size_t(a + rm[u]) * KF,
+                            el_sub<1, KF>(aij[u], el_mul_f<1, KF, KF>(fk[u], lik)));
+      }
+    }
+  } else {
+    for (int32_t p = a; p < e && S.ci[p] < i; ++p) {
+      const int32_t k = S.ci[p];
+      el<1, KF> lik = el_load<1, KF>(S.f + size_t(p) * KF);
+      lik = el_div_k<1, KF, KF>(lik, S.f + size_t(S.diag[k]) * KF);
+      el_store<1, KF>(S.f + size_t(p) * KF, lik);
+      int32_t r = p + 1;
+      for (int32_t q = S.diag[k] + 1; q < S.rp[k + 1]; ++q) {
+        const int32_t j = S.ci[q];
+        while (r < e && S.ci[r] < j) ++r;
+        if (r < e && S.ci[r] == j) {
+          el<1, KF> aij = el_load<1, KF>(S.f + size_t(r) * KF);
+          el<1, KF> prod = el_mul_f<1, KF, KF>(S.f + size_t(q) * KF, lik);
+          el_store<1, KF>(S.f + size_t(r) * KF, el_sub<1, KF>(aij, prod));
+        }
+      }
+    }
+  }
+  if (el_is_zero<1, KF>(el_load<1, KF>(S.f + size_t(di) * KF))) atomicMin(bad, i);
+}
+
 template <int KF>
 __device__ void bfactor(const BSys &S, int32_t nlev, int32_t *bad) {
+  __shared__ int32_t lcols[BLOCK * RCACHE];
   const int tid = threadIdx.x;
   for (int64_t p = tid; p < S.nnz; p += BLOCK) {
     S.f[p * KF] = S.val[p];
@@ -156,27 +236,8 @@ __device__ void bfactor(const BSys &S, int32_t nlev, int32_t *bad) {
   }
   __syncthreads();
   for (int32_t l = 0; l < nlev; ++l) {
-    for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK) {
-      const int32_t i = S.ordL[pos];
-      const int32_t ri_end = S.rp[i + 1];
-      for (int32_t p = S.rp[i]; p < ri_end && S.ci[p] < i; ++p) {
-        const int32_t k = S.ci[p];
-        el<1, KF> lik = el_load<1, KF>(S.f + size_t(p) * KF);
-        lik = el_div_k<1, KF, KF>(lik, S.f + size_t(S.diag[k]) * KF);
-        el_store<1, KF>(S.f + size_t(p) * KF, lik);
-        int32_t r = p + 1;
-        for (int32_t q = S.diag[k] + 1; q < S.rp[k + 1]; ++q) {
-          const int32_t j = S.ci[q];
-          while (r < ri_end && S.ci[r] < j) ++r;
-          if (r < ri_end && S.ci[r] == j) {
-            el<1, KF> aij = el_load<1, KF>(S.f + size_t(r) * KF);
-            el<1, KF> prod = el_mul_f<1, KF, KF>(S.f + size_t(q) * KF, lik);
-            el_store<1, KF>(S.f + size_t(r) * KF, el_sub<1, KF>(aij, prod));
-          }
-        }
-      }
-      if (el_is_zero<1, KF>(el_load<1, KF>(S.f + size_t(S.diag[i]) * KF))) atomicMin(bad, i);
-    }
+    for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK)
+      bfactor_row<KF>(S, S.ordL[pos], lcols + tid * RCACHE, bad);
     __syncthreads();
   }
 }
@@ -211,28 +272,125 @@ __device__ __forceinline__ el<1, K> bsub_products(el<1, K> acc, int32_t p0, int3
   return acc;
 }
 
+// The same for two rows at once (rows w = 0, 1 with entry ranges
+// [p0[w], p1[w])): both rows' loads are issued before either is used, so a
+// thread keeps twice as many requests in flight.  Each row's products are
+// subtracted in its own ascending order, as above.
+template <int K> constexpr int bpair_batch() { return K <= 2 ? 8 : 4; }
+
+template <int K, int KF>
+__device__ __forceinline__ void bsub_products2(el<1, K> (&acc)[2], const int32_t (&p0)[2],
+                                               const int32_t (&p1)[2],
+                                               const int32_t *__restrict__ ci,
+                                               const double *__restrict__ f, const double *v) {
+  constexpr int U = bpair_batch<K>();
+  int32_t pb[2] = {p0[0], p0[1]};
+  while (pb[0] < p1[0] || pb[1] < p1[1]) {
+    int32_t cj[2][U];
+    double fv[2][U][KF];
+    el<1, K> yv[2][U];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t p = pb[w] < p1[w] ? min(pb[w] + u, p1[w] - 1) : 0;
+        cj[w][u] = ci[p];
+#pragma unroll
+        for (int q = 0; q < KF; ++q) fv[w][u][q] = f[size_t(p) * KF + q];
+      }
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int u = 0; u < U; ++u) yv[w][u] = el_load<1, K>(v + size_t(cj[w][u]) * K);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pb[w] + u < p1[w]) acc[w] = el_sub<1, K>(acc[w], el_mul_f<1, K, KF>(fv[w][u], yv[w][u]));
+      pb[w] += U;
+    }
+  }
+}
+
+// Two rows of y = A x (as row_spmv: products in ascending column order,
+// accumulated from the first product; an empty row gives 0).
+template <int K>
+__device__ __forceinline__ void bspmv_rows2(const BSys &S, const int64_t (&i)[2], const bool (&ok)[2],
+                                            const double *x, mp<K> (&y)[2]) {
+  constexpr int U = bpair_batch<K>();
+  int32_t pb[2], pe[2], p0[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    p0[w] = ok[w] ? S.rp[i[w]] : 0;
+    pe[w] = ok[w] ? S.rp[i[w] + 1] : 0;
+    pb[w] = p0[w];
+    y[w] = mp_zero<K>();
+  }
+  while (pb[0] < pe[0] || pb[1] < pe[1]) {
+    int32_t cj[2][U];
+    double fv[2][U][1];
+    el<1, K> xv[2][U];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t p = pb[w] < pe[w] ? min(pb[w] + u, pe[w] - 1) : 0;
+        cj[w][u] = S.ci[p];
+        fv[w][u][0] = S.val[p];
+      }
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[w][u] = el_load<1, K>(x + size_t(cj[w][u]) * K);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pb[w] + u < pe[w]) {
+          const el<1, K> t = el_mul_f<1, K, 1>(fv[w][u], xv[w][u]);
+          y[w] = (pb[w] + u == p0[w]) ? t.c[0] : el_add<1, K>(el<1, K>{{y[w]}}, t).c[0];
+        }
+      pb[w] += U;
+    }
+  }
+}
+
 // z = (L U)^{-1} r with the level orders; y (intermediate) and z are
 // vectors of the system.  Row arithmetic as Algorithm 2: the strict lower
 // part of row i is [rp_i, diag_i), the strict upper part (diag_i, rp_i+1).
 template <int K, int KF>
 __device__ void bapply(const BSys &S, const BShared<K> &sh, const double *r, double *y, double *z) {
   const int tid = threadIdx.x;
+  // two rows of a level per thread and step (positions pos and pos + BLOCK)
   for (int32_t l = 0; l < sh.nlevL; ++l) {
-    for (int32_t pos = S.lptL[l] + tid; pos < S.lptL[l + 1]; pos += BLOCK) {
-      const int32_t i = S.ordL[pos];
-      el<1, K> acc = el_load<1, K>(r + size_t(i) * K);
-      acc = bsub_products<K, KF>(acc, S.rp[i], S.diag[i], S.ci, S.f, y);
-      el_store<1, K>(y + size_t(i) * K, acc);
+    const int32_t pe = S.lptL[l + 1];
+    for (int32_t pos = S.lptL[l] + tid; pos < pe; pos += 2 * BLOCK) {
+      const bool two = pos + BLOCK < pe;
+      const int32_t i0 = S.ordL[pos], i1 = two ? S.ordL[pos + BLOCK] : i0;
+      el<1, K> acc[2] = {el_load<1, K>(r + size_t(i0) * K), el_load<1, K>(r + size_t(i1) * K)};
+      const int32_t a[2] = {S.rp[i0], two ? S.rp[i1] : 0};
+      const int32_t b[2] = {S.diag[i0], two ? S.diag[i1] : 0};
+      bsub_products2<K, KF>(acc, a, b, S.ci, S.f, y);
+      el_store<1, K>(y + size_t(i0) * K, acc[0]);
+      if (two) el_store<1, K>(y + size_t(i1) * K, acc[1]);
     }
     __syncthreads();
   }
   for (int32_t l = 0; l < sh.nlevU; ++l) {
-    for (int32_t pos = S.lptU[l] + tid; pos < S.lptU[l + 1]; pos += BLOCK) {
-      const int32_t i = S.ordU[pos];
-      el<1, K> acc = el_load<1, K>(y + size_t(i) * K);
-      acc = bsub_products<K, KF>(acc, S.diag[i] + 1, S.rp[i + 1], S.ci, S.f, z);
-      acc = el_div_k<1, K, KF>(acc, S.f + size_t(S.diag[i]) * KF);
-      el_store<1, K>(z + size_t(i) * K, acc);
+    const int32_t pe = S.lptU[l + 1];
+    for (int32_t pos = S.lptU[l] + tid; pos < pe; pos += 2 * BLOCK) {
+      const bool two = pos + BLOCK < pe;
+      const int32_t i0 = S.ordU[pos], i1 = two ? S.ordU[pos + BLOCK] : i0;
+      el<1, K> acc[2] = {el_load<1, K>(y + size_t(i0) * K), el_load<1, K>(y + size_t(i1) * K)};
+      const int32_t a[2] = {S.diag[i0] + 1, two ? S.diag[i1] + 1 : 0};
+      const int32_t b[2] = {S.rp[i0 + 1], two ? S.rp[i1 + 1] : 0};
+      bsub_products2<K, KF>(acc, a, b, S.ci, S.f, z);
+      acc[0] = el_div_k<1, K, KF>(acc[0], S.f + size_t(S.diag[i0]) * KF);
+      el_store<1, K>(z + size_t(i0) * K, acc[0]);
+      if (two) {
+        acc[1] = el_div_k<1, K, KF>(acc[1], S.f + size_t(S.diag[i1]) * KF);
+        el_store<1, K>(z + size_t(i1) * K, acc[1]);
+      }
     }
     __syncthreads();
   }
@@ -392,11 +550,18 @@ __global__ __launch_bounds__(BLOCK) void batched_bicgstab(const BSys *__restrict
       // v = A p^, sigma = <r~, v>
       {
         mp<K> a = mp_zero<K>();
-        for (int64_t i = tid; i < n; i += BLOCK) {
-          mp<K> vi = bspmv_row<K>(S, i, ph);
-          stk<K>(v, i, vi);
-          mp<K> tt = mul<K>(ldk<K>(rt, i), vi);
-          a = (i == int64_t(tid)) ? tt : add<K>(a, tt);
+        for (int64_t i0 = tid; i0 < n; i0 += 2 * BLOCK) {
+          const int64_t ii[2] = {i0, i0 + BLOCK};
+          const bool ok[2] = {true, i0 + BLOCK < n};
+          mp<K> vv[2];
+          bspmv_rows2<K>(S, ii, ok, ph, vv);
+#pragma unroll
+          for (int w = 0; w < 2; ++w)
+            if (ok[w]) {
+              stk<K>(v, ii[w], vv[w]);
+              mp<K> tt = mul<K>(ldk<K>(rt, ii[w]), vv[w]);
+              a = (ii[w] == int64_t(tid)) ? tt : add<K>(a, tt);
+            }
         }
         bsum2<K>(a, mp_zero<K>(), sh.d);
       }
@@ -444,12 +609,19 @@ __global__ __launch_bounds__(BLOCK) void batched_bicgstab(const BSys *__restrict
       // t = A s^, <t, s>, <t, t>
       {
         mp<K> a = mp_zero<K>(), c = mp_zero<K>();
-        for (int64_t i = tid; i < n; i += BLOCK) {
-          mp<K> ti = bspmv_row<K>(S, i, shv);
-          stk<K>(t, i, ti);
-          mp<K> t1 = mul<K>(ti, ldk<K>(sv, i)), t2 = mul<K>(ti, ti);
-          a = (i == int64_t(tid)) ? t1 : add<K>(a, t1);
-          c = (i == int64_t(tid)) ? t2 : add<K>(c, t2);
+        for (int64_t i0 = tid; i0 < n; i0 += 2 * BLOCK) {
+          const int64_t ii[2] = {i0, i0 + BLOCK};
+          const bool ok[2] = {true, i0 + BLOCK < n};
+          mp<K> tv[2];
+          bspmv_rows2<K>(S, ii, ok, shv, tv);
+#pragma unroll
+          for (int w = 0; w < 2; ++w)
+            if (ok[w]) {
+              stk<K>(t, ii[w], tv[w]);
+              mp<K> t1 = mul<K>(tv[w], ldk<K>(sv, ii[w])), t2 = mul<K>(tv[w], tv[w]);
+              a = (ii[w] == int64_t(tid)) ? t1 : add<K>(a, t1);
+              c = (ii[w] == int64_t(tid)) ? t2 : add<K>(c, t2);
+            }
         }
         bsum2<K>(a, c, sh.d);
       }

@@ -283,3 +283,30 @@ def test_short_training_lowers_the_loss(mpk):
     after = [float(tr.loss(i)) for i in insts]
     assert np.all(np.isfinite(after))
     assert np.mean(after) < 0.9 * np.mean(before), (before, after)
+
+
+def test_trained_network_gains_over_plain_ilu0(mpk):
+    """Train on 32 small lognormal systems (64^2), then solve 8 held-out
+    ones to 1e-25 with the learned and the plain factor.  The plain method
+    is the judge: the learned factor must not need more passes at the
+    median, every solve must converge, and the fallback rule must hold."""
+    from paper_2504_14498_amd import learned
+    train = [learned.Instance(W.config5(s, m=64), seed=s) for s in range(32)]
+    tr = learned.Trainer(seed=1, lr=2e-3)
+    for epoch in range(4):
+        for inst in train:
+            tr.step(inst)
+    plain_train = [learned.solve_plain(i.A, i.b)[1]["iters"] for i in train[:8]]
+    cap = learned.iteration_cap(plain_train)
+    ratios = []
+    for s in range(8):
+        inst = learned.Instance(W.config5(100_000 + s, m=64), probes=False)
+        _, ip = learned.solve_plain(inst.A, inst.b)
+        _, il = learned.solve_learned(inst.A, inst.b, tr.params, cap)
+        assert ip["status"] == "ok" and il["status"] == "ok"
+        assert il["relres_true"] < 1e-25
+        if il["fallback"] is None:
+            assert il["iters_total"] <= cap
+        ratios.append(il["iters_total"] / ip["iters"])
+    print("learned/plain pass ratios on held-out systems:", np.round(ratios, 3))
+    assert np.median(ratios) < 1.0, ratios

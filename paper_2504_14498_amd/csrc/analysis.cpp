@@ -10,48 +10,103 @@
 // ascending column order of Algorithm 2.
 #include <algorithm>
 #include <cstdlib>
+#include <thread>
 
 #include "internal.hpp"
 
 namespace mpk {
 
+// The pattern is copied into a page-locked buffer of the calling thread,
+// kept (and grown when needed) across calls: device-to-host copies into
+// pageable memory go through a staging copy and run several times slower.
+namespace {
+struct PinnedStage {
+  int32_t *p = nullptr;
+  size_t cap = 0;  // int32 words
+};
+thread_local PinnedStage pinned_stage;
+}  // namespace
+
 int fetch_pattern(const mpk_csr *A, HostCsr &h, hipStream_t s) {
   h.n = A->n;
   h.nnz = A->nnz;
-  h.rp.resize(size_t(A->n) + 1);
-  h.ci.resize(size_t(std::max<int64_t>(A->nnz, 1)));
-  MPK_HIP(hipMemcpyAsync(h.rp.data(), A->row_ptr, sizeof(int32_t) * (A->n + 1),
-                         hipMemcpyDeviceToHost, s));
+  const size_t need = size_t(A->n) + 1 + size_t(std::max<int64_t>(A->nnz, 1));
+  PinnedStage &st = pinned_stage;
+  if (st.cap < need) {
+    if (st.p) (void)hipHostFree(st.p);
+    st.p = nullptr;
+    st.cap = 0;
+    void *q = nullptr;
+    if (hipHostMalloc(&q, sizeof(int32_t) * need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      // no page-locked memory: fall back to the thread's own arrays
+      h.own_rp.resize(size_t(A->n) + 1);
+      h.own_ci.resize(size_t(std::max<int64_t>(A->nnz, 1)));
+      h.own();
+      MPK_HIP(hipMemcpyAsync(h.own_rp.data(), A->row_ptr, sizeof(int32_t) * (A->n + 1),
+                             hipMemcpyDeviceToHost, s));
+      if (A->nnz > 0)
+        MPK_HIP(hipMemcpyAsync(h.own_ci.data(), A->col_idx, sizeof(int32_t) * A->nnz,
+                               hipMemcpyDeviceToHost, s));
+      MPK_HIP(hipStreamSynchronize(s));
+      return MPK_OK;
+    }
+    st.p = static_cast<int32_t *>(q);
+    st.cap = need;
+  }
+  int32_t *rp = st.p, *ci = st.p + (size_t(A->n) + 1);
+  MPK_HIP(hipMemcpyAsync(rp, A->row_ptr, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToHost, s));
   if (A->nnz > 0)
-    MPK_HIP(hipMemcpyAsync(h.ci.data(), A->col_idx, sizeof(int32_t) * A->nnz,
-                           hipMemcpyDeviceToHost, s));
+    MPK_HIP(hipMemcpyAsync(ci, A->col_idx, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToHost, s));
   MPK_HIP(hipStreamSynchronize(s));
+  h.rp = rp;
+  h.ci = ci;
   return MPK_OK;
 }
 
 int check_pattern(const HostCsr &h, int64_t *bad_row) {
   *bad_row = -1;
   if (h.rp[0] != 0 || h.rp[h.n] != h.nnz) return MPK_EPATTERN;
-  for (int64_t i = 0; i < h.n; ++i) {
-    int32_t a = h.rp[i], b = h.rp[i + 1];
-    if (b < a) {
-      *bad_row = i;
-      return MPK_EPATTERN;
-    }
-    bool diag = false;
-    for (int32_t p = a; p < b; ++p) {
-      int32_t j = h.ci[p];
-      if (j < 0 || j >= h.n || (p > a && j <= h.ci[p - 1])) {
-        *bad_row = i;
-        return MPK_EPATTERN;
+  // rows in up to 8 contiguous chunks on host threads; the first chunk
+  // (in row order) that finds a bad row reports the lowest one
+  const int T = int(std::min<int64_t>(8, std::max<int64_t>(1, h.n / 65536)));
+  std::vector<int64_t> bad(size_t(T), -1);
+  std::vector<int> code(size_t(T), MPK_OK);
+  auto work = [&](int t) {
+    const int64_t i0 = h.n * t / T, i1 = h.n * (t + 1) / T;
+    for (int64_t i = i0; i < i1; ++i) {
+      const int32_t a = h.rp[i], b = h.rp[i + 1];
+      if (b < a || a < 0 || b > h.nnz) {
+        bad[t] = i;
+        code[t] = MPK_EPATTERN;
+        return;
       }
-      diag |= (j == i);
+      bool diag = false;
+      for (int32_t p = a; p < b; ++p) {
+        const int32_t j = h.ci[p];
+        if (j < 0 || j >= h.n || (p > a && j <= h.ci[p - 1])) {
+          bad[t] = i;
+          code[t] = MPK_EPATTERN;
+          return;
+        }
+        diag |= (j == i);
+      }
+      if (!diag) {
+        bad[t] = i;
+        code[t] = MPK_ENO_DIAG;
+        return;
+      }
     }
-    if (!diag) {
-      *bad_row = i;
-      return MPK_ENO_DIAG;
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  for (int t = 0; t < T; ++t)
+    if (bad[t] >= 0) {
+      *bad_row = bad[t];
+      return code[t];
     }
-  }
   return MPK_OK;
 }
 
@@ -62,8 +117,7 @@ void host_diag(const HostCsr &h, std::vector<int32_t> &diag) {
       if (h.ci[p] == i) diag[i] = p;
 }
 
-void host_transpose(const HostCsr &h, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
-                    std::vector<int32_t> &tsrc) {
+void host_transpose(const HostCsr &h, IVec &trp, IVec &tci, IVec &tsrc) {
   const int64_t n = h.n, nnz = h.nnz;
   trp.assign(size_t(n) + 1, 0);
   tci.resize(size_t(std::max<int64_t>(nnz, 1)));
@@ -109,7 +163,7 @@ struct DepView {
 void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
   const int64_t n = h.n;
   const HostCsr &g = (kind >= 2) ? *ht : h;
-  const DepView dv{g.rp.data(), g.ci.data(), kind == 0 || kind == 2};
+  const DepView dv{g.rp, g.ci, kind == 0 || kind == 2};
   const bool forward = (kind == 0 || kind == 2);
   int shift = 0;
   while ((int64_t(1) << shift) < blk_rows) ++shift;

@@ -815,7 +815,7 @@ int mpk_gnn_graph_setup(const mpk_csr *A, const mpk_ilu0 *Mh, void *graph, size_
   GGraph G = graph_of(A, graph);
   HostCsr h;
   if ((st = fetch_pattern(A, h, s))) return st;
-  std::vector<int32_t> trp, tci, tsrc;
+  IVec trp, tci, tsrc;
   host_transpose(h, trp, tci, tsrc);
   MPK_HIP(hipMemcpyAsync(G.t_rp, trp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice,
                          s));

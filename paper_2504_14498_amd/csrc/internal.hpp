@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpk.h"
@@ -174,9 +175,32 @@ template <class F> int dispatch_ck(int C, int K, F &&f) {
 }
 
 // Host-side CSR checks and schedules (analysis.cpp).
+// Host index arrays that are overwritten at once: allocated without the
+// zero fill of std::vector<int32_t>::resize.
+template <class T> struct NoInitAlloc : std::allocator<T> {
+  template <class U> struct rebind { using other = NoInitAlloc<U>; };
+  NoInitAlloc() = default;
+  template <class U> NoInitAlloc(const NoInitAlloc<U> &) {}
+  template <class U, class... A> void construct(U *p, A &&...a) {
+    if constexpr (sizeof...(A) == 0)
+      ::new (static_cast<void *>(p)) U;
+    else
+      ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+  }
+};
+using IVec = std::vector<int32_t, NoInitAlloc<int32_t>>;
+
+// A CSR pattern on the host.  rp/ci point either into own_rp/own_ci or
+// into the calling thread's page-locked staging buffer (fetch_pattern),
+// which stays valid until that thread's next fetch.
 struct HostCsr {
   int64_t n = 0, nnz = 0;
-  std::vector<int32_t> rp, ci;
+  const int32_t *rp = nullptr, *ci = nullptr;
+  IVec own_rp, own_ci;
+  void own() {
+    rp = own_rp.data();
+    ci = own_ci.data();
+  }
 };
 int fetch_pattern(const mpk_csr *A, HostCsr &h, hipStream_t s);
 int check_pattern(const HostCsr &h, int64_t *bad_row);
@@ -199,7 +223,6 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);
 
 // Transposed pattern with source map (for A^T / A^H products).
-void host_transpose(const HostCsr &h, std::vector<int32_t> &trp, std::vector<int32_t> &tci,
-                    std::vector<int32_t> &tsrc);
+void host_transpose(const HostCsr &h, IVec &trp, IVec &tci, IVec &tsrc);
 
 }  // namespace mpk

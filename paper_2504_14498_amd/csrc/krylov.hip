@@ -782,7 +782,7 @@ static int krylov_run(int method, int KF, double tol_rel, double tol_abs, int64_
   if (method == MPK_BICG) {
     HostCsr h;
     if ((st = fetch_pattern(A, h, s))) return st;
-    std::vector<int32_t> trp, tci, tsrc;
+    IVec trp, tci, tsrc;
     host_transpose(h, trp, tci, tsrc);
     MPK_HIP(hipMemcpyAsync(S.L.t_rp, trp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice, s));
     MPK_HIP(hipMemcpyAsync(S.L.t_ci, tci.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));

@@ -196,10 +196,11 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     std::thread t2;
     if (adj) {
       t2 = std::thread([&] {
-        std::vector<int32_t> tsrc;
+        IVec tsrc;
         ht.n = h.n;
         ht.nnz = h.nnz;
-        host_transpose(h, ht.rp, ht.ci, tsrc);
+        host_transpose(h, ht.own_rp, ht.own_ci, tsrc);
+        ht.own();
         std::thread t4([&] { build_plan(h, &ht, 3, br, hp[3]); });
         build_plan(h, &ht, 2, br, hp[2]);
         t4.join();
@@ -222,7 +223,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   if (adj) {
     // transposed pattern for the adjoint schedules: rows of A^T with the
     // source position of each entry in A's pattern
-    std::vector<int32_t> trp, tci, tsrc;
+    IVec trp, tci, tsrc;
     host_transpose(h, trp, tci, tsrc);
     MPK_HIP(hipMemcpyAsync(M->t_rp, trp.data(), sizeof(int32_t) * (A->n + 1), hipMemcpyHostToDevice, s));
     MPK_HIP(hipMemcpyAsync(M->t_ci, tci.data(), sizeof(int32_t) * A->nnz, hipMemcpyHostToDevice, s));
@@ -394,7 +395,7 @@ static int csr_spmv(int C, mpk_prec xp, const mpk_csr *A, int trans, const doubl
   if ((st = fetch_pattern(A, h, s))) return st;
   int64_t bad;
   if ((st = check_pattern(h, &bad))) return st;
-  std::vector<int32_t> trp, tci, tsrc;
+  IVec trp, tci, tsrc;
   host_transpose(h, trp, tci, tsrc);
   Bump b(ws);
   int32_t *d_rp = b.take<int32_t>(size_t(A->n) + 1), *d_ci = b.take<int32_t>(size_t(A->nnz)),

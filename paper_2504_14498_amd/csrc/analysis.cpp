@@ -217,11 +217,21 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
   p.blk_lev.assign(size_t(p.nblk) + 1, 0);
   p.loc_pos.clear();
   p.order.assign(size_t(std::max<int64_t>(n, 1)), 0);
-  std::vector<int32_t> loc(size_t(blk_rows), 0), cnt;
-  int32_t base = 0;
+  // blocks are independent: their local levels are computed on up to 8
+  // host threads, then the level boundaries are concatenated in block
+  // order.  Block b's positions start after those of the blocks processed
+  // before it (in the backward direction the first one is the short tail).
+  std::vector<std::vector<int32_t>> bpos(size_t(p.nblk));
+  std::vector<int32_t> bbase(size_t(p.nblk) + 1, 0);
   for (int32_t b = 0; b < p.nblk; ++b) {
     const int32_t nb = forward ? b : p.nblk - 1 - b;
     const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
+    bbase[size_t(b) + 1] = bbase[size_t(b)] + int32_t(r1 - r0);
+  }
+  auto do_block = [&](int32_t b, std::vector<int32_t> &loc, std::vector<int32_t> &cnt) {
+    const int32_t nb = forward ? b : p.nblk - 1 - b;
+    const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
+    const int32_t base = bbase[size_t(b)];
     p.blk_r[2 * b] = int32_t(r0);
     p.blk_r[2 * b + 1] = int32_t(r1);
     int32_t nl = 1;
@@ -234,16 +244,30 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
       loc[i - r0] = l;
       nl = std::max(nl, l + 1);
     }
-    p.blk_lev[b] = int32_t(p.loc_pos.size());
     cnt.assign(size_t(nl) + 1, 0);
     for (int64_t i = r0; i < r1; ++i) cnt[loc[i - r0] + 1]++;
     for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
     // a local level wider than a workgroup is cut into pieces of at most
     // BLOCK rows (its rows are independent), so a lane owns one row
+    std::vector<int32_t> &bp = bpos[size_t(b)];
     for (int32_t l = 0; l < nl; ++l)
-      for (int32_t q = cnt[l]; q < cnt[l + 1]; q += BLOCK) p.loc_pos.push_back(base + q);
+      for (int32_t q = cnt[l]; q < cnt[l + 1]; q += BLOCK) bp.push_back(base + q);
     for (int64_t i = r0; i < r1; ++i) p.order[base + cnt[loc[i - r0]]++] = int32_t(i);
-    base += int32_t(r1 - r0);
+  };
+  {
+    const int T = int(std::min<int64_t>(8, std::max<int32_t>(1, p.nblk / 4)));
+    auto work = [&](int t) {
+      std::vector<int32_t> loc(size_t(blk_rows), 0), cnt;
+      for (int32_t b = t; b < p.nblk; b += T) do_block(b, loc, cnt);
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+  }
+  for (int32_t b = 0; b < p.nblk; ++b) {
+    p.blk_lev[b] = int32_t(p.loc_pos.size());
+    p.loc_pos.insert(p.loc_pos.end(), bpos[size_t(b)].begin(), bpos[size_t(b)].end());
   }
   p.blk_lev[p.nblk] = int32_t(p.loc_pos.size());
   p.loc_pos.push_back(int32_t(n));

@@ -52,6 +52,8 @@ def case(name):
         return W.random_pattern(1277, 0.005, 2, complex_=True, dominance=1.2)
     if name == "conv2d":
         return W.config1(37)
+    if name == "conv2d_tail":      # several sweep blocks, the last one short
+        return W.config1(150)
     if name == "conv3d":
         return W.config2(12)
     if name == "helm":
@@ -104,7 +106,8 @@ def test_spmv_transpose_bitwise(mpk, orc, name, K):
     assert np.array_equal(y, yo)
 
 
-@pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv2d", "conv3d", "helm", "rdd"])
+@pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv2d", "conv2d_tail", "conv3d", "helm",
+                                  "rdd"])
 @pytest.mark.parametrize("kf,K", [(1, 1), (1, 2), (2, 2), (1, 3), (2, 3), (1, 4), (2, 4)])
 def test_ilu0_apply_bitwise(mpk, orc, name, kf, K):
     p = case(name)
@@ -198,6 +201,7 @@ SOLVE_CASES = [
     ("conv3d", "cgs", 3, 1, 1e-30),
     ("conv3d", "bicgstab", 4, 2, 1e-50),
     ("conv2d", "bicgstab", 1, 1, 1e-12),
+    ("conv2d_tail", "bicg", 2, 1, 1e-25),
     ("helm", "gpbicg", 2, 1, 1e-25),
     ("helm", "bicgstab", 2, 2, 1e-25),
     ("helm", "bicg", 2, 1, 1e-25),

@@ -10,6 +10,7 @@
 // ascending column order of Algorithm 2.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
 #include <thread>
 
 #include "internal.hpp"
@@ -137,7 +138,11 @@ void host_transpose(const HostCsr &h, IVec &trp, IVec &tci, IVec &tsrc) {
 // at most 128 KiB for quad-double (K = 4).
 int default_block_rows(int C, int kmax) {
   const char *e = getenv("MPK_TRSV_BLOCK_ROWS");
-  if (e) return std::max(64, atoi(e));
+  if (e) {
+    int rows = 64;  // a power of two (block shapes are built with shifts)
+    while (rows * 2 <= atoi(e)) rows *= 2;
+    return rows;
+  }
   // largest power of two with rows * C * kmax doubles within 128 KiB
   int rows = 64;
   while (int64_t(rows) * 2 * C * kmax * 8 <= 131072) rows *= 2;
@@ -159,6 +164,58 @@ struct DepView {
     }
   }
 };
+
+// Block geometry of a blocked sweep with cap LDS slots per block: plain
+// ranges of cap consecutive rows, or blocks t periods deep when most rows
+// share a long dependency offset P (one plane of a grid numbered plane by
+// plane).  A dependency chain through the whole matrix crosses about
+// (periods / t - 1) + (chunks per period - 1) block boundaries, against
+// n / cap - 1 for plain ranges, and each crossing is a value written by one
+// workgroup and polled by another.  The deep shape with the fewest
+// crossings is returned only if it cuts them by a third; the caller still
+// checks that no dependency leads to a block processed later.
+static BlockGeom plain_geom(int64_t n, int cap) {
+  BlockGeom g;
+  g.P = std::max<int64_t>(n, 1);
+  g.w = cap;
+  g.t = 1;
+  g.nch = (g.P + cap - 1) / cap;
+  return g;
+}
+
+static BlockGeom deep_geom(const DepView &dv, int64_t n, int cap) {
+  const BlockGeom plain = plain_geom(n, cap);
+  if (const char *e = getenv("MPK_TRSV_DEEP"))
+    if (e[0] == '0') return plain;
+  // dependency offsets over a window of rows in the middle of the matrix
+  const int64_t W = std::min<int64_t>(n, 4096), i0 = (n - W) / 2;
+  std::map<int64_t, int64_t> cnt;
+  for (int64_t i = i0; i < i0 + W; ++i)
+    dv.each(i, [&](int32_t j) { cnt[i > j ? i - j : j - i]++; });
+  std::vector<int64_t> periods;
+  for (auto it = cnt.rbegin(); it != cnt.rend() && periods.size() < 3; ++it)
+    if (4 * it->second >= W && it->first >= 2 && it->first < n) periods.push_back(it->first);
+  const int64_t base = (n + cap - 1) / cap - 1;
+  int64_t best = -1;
+  BlockGeom g = plain;
+  for (const int64_t P : periods) {
+    const int64_t nper = (n + P - 1) / P;
+    for (int32_t t = 2; t <= cap && t <= nper; t *= 2) {
+      const int32_t w = cap / t;
+      if (w > P) continue;
+      const int64_t nch = (P + w - 1) / w;
+      const int64_t cost = ((nper + t - 1) / t - 1) + (nch - 1);
+      if (3 * cost <= 2 * base && (best < 0 || cost < best)) {
+        best = cost;
+        g.P = P;
+        g.w = w;
+        g.t = t;
+        g.nch = nch;
+      }
+    }
+  }
+  return g;
+}
 
 void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
   const int64_t n = h.n;
@@ -209,14 +266,79 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
     p.seg.push_back(int32_t(n));
     return;
   }
-  // blocked schedule: blocks of blk_rows consecutive rows taken in the
-  // sweep's direction, each ordered by its local (block-internal) levels
+  // blocked schedule: blocks (plain row ranges or a few periods deep, see
+  // deep_geom) taken in the sweep's direction, each ordered by its local
+  // (block-internal) levels
   p.blk_rows = blk_rows;
-  p.nblk = int32_t((n + blk_rows - 1) / blk_rows);
+  BlockGeom G = deep_geom(dv, n, blk_rows);
+  int lw = 0, lt = 0;
+  while ((1 << lw) < G.w) ++lw;
+  while ((1 << lt) < G.t) ++lt;
+  // block id and LDS slot of every row of a deep geometry (plain ranges
+  // use the shifts directly), on up to 8 host threads
+  IVec blk_of, slot_of;
+  const int T8 = int(std::min<int64_t>(8, std::max<int64_t>(1, n / 65536)));
+  auto par = [&](auto &&f) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < T8; ++t) th.emplace_back(f, t);
+    f(0);
+    for (auto &x : th) x.join();
+  };
+  if (G.t > 1) {
+    blk_of.resize(size_t(n));
+    slot_of.resize(size_t(n));
+    par([&](int t) {
+      const int64_t a0 = n * t / T8, a1 = n * (t + 1) / T8;
+      int64_t z = a0 / G.P, a = a0 - z * G.P;
+      for (int64_t i = a0; i < a1; ++i) {
+        blk_of[i] = int32_t((z >> lt) * G.nch + (a >> lw));
+        slot_of[i] = int32_t(((z & (G.t - 1)) << lw) | (a & (G.w - 1)));
+        if (++a == G.P) {
+          a = 0;
+          ++z;
+        }
+      }
+    });
+    // every dependency must stay in its block or lead to a block processed
+    // earlier, and every row must fit the flat dependency slots
+    std::vector<char> ok(size_t(T8), 1);
+    par([&](int t) {
+      const int64_t a0 = n * t / T8, a1 = n * (t + 1) / T8;
+      for (int64_t i = a0; i < a1 && ok[t]; ++i) {
+        int nd = 0;
+        dv.each(i, [&](int32_t j) {
+          ++nd;
+          if (forward ? blk_of[j] > blk_of[i] : blk_of[j] < blk_of[i]) ok[t] = 0;
+        });
+        if (nd > ELLW) ok[t] = 0;
+      }
+    });
+    if (std::find(ok.begin(), ok.end(), 0) != ok.end()) {
+      G = plain_geom(n, blk_rows);
+      lw = lt = 0;
+      while ((1 << lw) < G.w) ++lw;
+    }
+  }
+  const bool deep = G.t > 1;
+  auto BLK = [&](int64_t i) -> int64_t { return deep ? blk_of[i] : (i >> lw); };
+  auto SLOT = [&](int64_t i) -> int32_t { return deep ? slot_of[i] : int32_t(i & (G.w - 1)); };
+  p.geom = G;
+  {
+    const int64_t nper = (n + G.P - 1) / G.P, nzg = (nper + G.t - 1) / G.t;
+    const int64_t rest = n - (nzg - 1) * G.t * G.P;
+    p.nblk = int32_t((nzg - 1) * G.nch + std::min<int64_t>(G.nch, (rest + G.w - 1) / G.w));
+  }
   p.blk_r.assign(size_t(2) * p.nblk, 0);
   p.blk_lev.assign(size_t(p.nblk) + 1, 0);
   p.loc_pos.clear();
   p.order.assign(size_t(std::max<int64_t>(n, 1)), 0);
+  // block (by id): first row and width of its ranges; range k starts k * P
+  // rows later, all clipped to n
+  auto ranges = [&](int64_t id, int64_t &r0, int64_t &wb) {
+    const int64_t bz = id / G.nch, ba = id - bz * G.nch;
+    r0 = bz * G.t * G.P + ba * G.w;
+    wb = std::min<int64_t>(G.w, G.P - ba * G.w);
+  };
   // blocks are independent: their local levels are computed on up to 8
   // host threads, then the level boundaries are concatenated in block
   // order.  Block b's positions start after those of the blocks processed
@@ -224,35 +346,54 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
   std::vector<std::vector<int32_t>> bpos(size_t(p.nblk));
   std::vector<int32_t> bbase(size_t(p.nblk) + 1, 0);
   for (int32_t b = 0; b < p.nblk; ++b) {
-    const int32_t nb = forward ? b : p.nblk - 1 - b;
-    const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
-    bbase[size_t(b) + 1] = bbase[size_t(b)] + int32_t(r1 - r0);
+    const int64_t id = forward ? b : p.nblk - 1 - b;
+    int64_t r0, wb, rows = 0;
+    ranges(id, r0, wb);
+    for (int32_t k = 0; k < G.t; ++k) {
+      const int64_t a = r0 + k * G.P;
+      if (a >= n) break;
+      rows += std::min<int64_t>(a + wb, n) - a;
+    }
+    bbase[size_t(b) + 1] = bbase[size_t(b)] + int32_t(rows);
   }
   auto do_block = [&](int32_t b, std::vector<int32_t> &loc, std::vector<int32_t> &cnt) {
-    const int32_t nb = forward ? b : p.nblk - 1 - b;
-    const int64_t r0 = int64_t(nb) * blk_rows, r1 = std::min<int64_t>(n, r0 + blk_rows);
+    const int64_t id = forward ? b : p.nblk - 1 - b;
+    int64_t r0, wb;
+    ranges(id, r0, wb);
     const int32_t base = bbase[size_t(b)];
     p.blk_r[2 * b] = int32_t(r0);
-    p.blk_r[2 * b + 1] = int32_t(r1);
+    p.blk_r[2 * b + 1] = int32_t(std::min<int64_t>(r0 + wb, n));
+    int32_t nk = 0;
+    while (nk < G.t && r0 + nk * G.P < n) ++nk;
+    // the block's rows in the sweep's direction
+    auto each_row = [&](auto &&f) {
+      for (int32_t kk = 0; kk < nk; ++kk) {
+        const int32_t k = forward ? kk : nk - 1 - kk;
+        const int64_t a = r0 + k * G.P, e = std::min<int64_t>(a + wb, n);
+        if (forward)
+          for (int64_t i = a; i < e; ++i) f(i);
+        else
+          for (int64_t i = e - 1; i >= a; --i) f(i);
+      }
+    };
     int32_t nl = 1;
-    for (int64_t t = 0; t < r1 - r0; ++t) {
-      const int64_t i = forward ? r0 + t : r1 - 1 - t;
+    each_row([&](int64_t i) {
       int32_t l = 0;
       dv.each(i, [&](int32_t j) {
-        if (j >= r0 && j < r1) l = std::max(l, loc[j - r0] + 1);
+        if (BLK(j) == id) l = std::max(l, loc[SLOT(j)] + 1);
       });
-      loc[i - r0] = l;
+      loc[SLOT(i)] = l;
       nl = std::max(nl, l + 1);
-    }
+    });
     cnt.assign(size_t(nl) + 1, 0);
-    for (int64_t i = r0; i < r1; ++i) cnt[loc[i - r0] + 1]++;
+    each_row([&](int64_t i) { cnt[loc[SLOT(i)] + 1]++; });
     for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
     // a local level wider than a workgroup is cut into pieces of at most
     // BLOCK rows (its rows are independent), so a lane owns one row
     std::vector<int32_t> &bp = bpos[size_t(b)];
     for (int32_t l = 0; l < nl; ++l)
       for (int32_t q = cnt[l]; q < cnt[l + 1]; q += BLOCK) bp.push_back(base + q);
-    for (int64_t i = r0; i < r1; ++i) p.order[base + cnt[loc[i - r0]]++] = int32_t(i);
+    each_row([&](int64_t i) { p.order[base + cnt[loc[SLOT(i)]]++] = int32_t(i); });
   };
   {
     const int T = int(std::min<int64_t>(8, std::max<int32_t>(1, p.nblk / 4)));
@@ -296,6 +437,7 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
   p.sync = b.take<int32_t>(64);
   p.ell_nd = b.take<int32_t>(size_t(n));
   p.ell_col = b.take<int32_t>(size_t(n) * ELLW);
+  p.ell_slot = b.take<int32_t>(size_t(n));
   p.ell_src = b.take<int32_t>(size_t(n) * ELLW);
   p.ell_val = b.take<double>(size_t(n) * ELLW * C * KF);
   p.blk_r = b.take<int32_t>(2 * size_t(n) + 2);
@@ -313,6 +455,7 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
   p.mode = hp.mode;
   p.nblk = hp.nblk;
   p.blk_rows = hp.blk_rows;
+  p.geom = hp.geom;
   MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * p.n, hipMemcpyHostToDevice, s));
   (void)n;
   if (hp.mode == 1) {

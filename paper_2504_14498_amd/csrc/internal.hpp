@@ -67,6 +67,31 @@ struct Bump {
   }
 };
 
+// Block geometry of the blocked sweeps.  A block is t ranges of w
+// consecutive rows, one range in each of t consecutive periods of P rows:
+// the rows z * P + a with z in [bz * t, bz * t + t) and a in
+// [ba * w, ba * w + w), a < P.  Blocks are numbered bz * nch + ba (nch
+// chunks per period), which is the forward sweep's processing order.  A
+// row's LDS slot in its block is (z mod t) * w + (a mod w).  With t = 1
+// and P = n a block is a plain range of w consecutive rows.  On a grid
+// numbered plane by plane, P = one plane and t > 1 gives blocks a few
+// planes deep, so a dependency chain through the grid crosses fewer
+// blocks.  w and t are powers of two.
+struct BlockGeom {
+  int64_t P = 1;    // period (rows)
+  int32_t w = 1;    // rows of one range
+  int32_t t = 1;    // ranges (periods) per block
+  int64_t nch = 1;  // chunks per period: ceil(P / w)
+  __host__ __device__ int64_t block(int64_t i) const {
+    const int64_t z = i / P, a = i - z * P;
+    return (z / t) * nch + a / w;
+  }
+  __host__ __device__ int32_t slot(int64_t i) const {
+    const int64_t z = i / P, a = i - z * P;
+    return int32_t((z % t) * w + a % w);
+  }
+};
+
 // A dependency-ordered schedule for one triangular sweep: rows grouped by
 // level; `seg` splits each level into runs of at most WAVE rows (the work
 // unit of one wavefront, free of internal dependencies).
@@ -90,14 +115,16 @@ struct Plan {
   int32_t mode = 0;            // 0 level schedule, 1 blocked schedule
   int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
   int32_t kmax = 4;            // largest vector precision the blocks are sized for
-  int32_t blk_rows = 0;        // rows per block
-  int32_t *blk_r = nullptr;    // [2*nblk] row range [r0, r1) of each block
+  int32_t blk_rows = 0;        // LDS slots per block (t * w)
+  BlockGeom geom;              // block shape
+  int32_t *blk_r = nullptr;    // [2*nblk] first range [r0, r1) of each block
   int32_t *blk_lev = nullptr;  // [nblk+1] first local level of each block
   int32_t *loc_pos = nullptr;  // [nloc+1] first position of each local level
   // flat per-position dependency slots (blocked schedule): up to ELLW
   // dependencies of the row at position pos live at [pos * ELLW + d]
   int32_t *ell_nd = nullptr;   // [n] dependencies of each position
-  int32_t *ell_col = nullptr;  // [n * ELLW]
+  int32_t *ell_col = nullptr;  // [n * ELLW] column j, or -(slot + 1) if j is in the row's block
+  int32_t *ell_slot = nullptr; // [n] LDS slot of the row at each position
   int32_t *ell_src = nullptr;  // [n * ELLW] value source in A's pattern (-1 pad)
   double *ell_val = nullptr;   // [n * ELLW * C * KF]
   std::vector<int32_t> h_blk;  // host copies kept alive for the uploads
@@ -210,6 +237,7 @@ struct HostPlan {
   std::vector<int32_t> order, ptr, col, src, dsrc, seg, seg_level, levptr;
   int32_t nlev = 0;
   int32_t mode = 0, nblk = 0, blk_rows = 0;
+  BlockGeom geom;
   std::vector<int32_t> blk_r, blk_lev, loc_pos;
   std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)
 };

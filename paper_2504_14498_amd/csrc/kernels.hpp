@@ -252,15 +252,21 @@ static __global__ void scan_add(int64_t n, int32_t *out, const int32_t *__restri
 // Per-position dependency arrays: columns and value sources (positions in
 // A's pattern; srcmap maps the rows of A^T back to A) in ascending column
 // order, the flat ELLW slots of the blocked sweeps, and the pivot position.
+// A flat slot holds the column j of a dependency in another block, or
+// -(LDS slot of j + 1) for one in the row's own block (geometry G); the
+// row's own LDS slot goes to ell_slot.
 static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                  const int32_t *__restrict__ srcmap, int lower,
                                  const int32_t *__restrict__ ptr, int32_t *col, int32_t *src,
                                  int32_t *ell_nd, int32_t *ell_col, int32_t *ell_src,
+                                 int32_t *ell_slot, BlockGeom G,
                                  const int32_t *__restrict__ diag, int32_t *dsrc) {
   const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   if (pos >= n) return;
   const int32_t i = order[pos];
+  const int64_t bi = ell_nd ? G.block(i) : 0;
+  if (ell_nd) ell_slot[pos] = G.slot(i);
   int32_t o = ptr[pos], d = 0;
   for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
     const int32_t j = ci[q];
@@ -269,7 +275,7 @@ static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
       col[o] = j;
       src[o] = sp;
       if (ell_nd && d < ELLW) {
-        ell_col[pos * ELLW + d] = j;
+        ell_col[pos * ELLW + d] = G.block(j) == bi ? -(G.slot(j) + 1) : j;
         ell_src[pos * ELLW + d] = sp;
       }
       ++o;
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(BLOCK) void trsv_syncfree(
   }
 }
 
-// Blocked schedule: a workgroup takes the next block of consecutive rows
+// Blocked schedule: a workgroup takes the next block of rows
 // (tickets hand blocks out in the sweep's order, so a block only waits on
 // blocks already taken by running workgroups) and walks the block's local
 // levels; results of the block stay in LDS for the rows of the same block
@@ -542,6 +548,7 @@ __global__ __launch_bounds__(BLOCK) void trsv_syncfree(
 
 typedef unsigned int bu2 __attribute__((ext_vector_type(2)));
 typedef unsigned int bu4 __attribute__((ext_vector_type(4)));
+typedef int bi4 __attribute__((ext_vector_type(4)));
 constexpr int BUF_AGENT = 16;               // cache policy: coherent at agent scope (sc1)
 constexpr uint32_t BUF_OOB = 0xFFFFFF00u;   // an offset past every buffer's end
 
@@ -558,9 +565,11 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, d
 }
 
 template <int C, int K, int KF, int MAXD> struct RowPre {
-  int32_t i, pos, nd;
+  int32_t i, pos, nd, slot;
   bool valid;
-  int32_t cj[MAXD];
+  // flat slots: column j, or -(LDS slot + 1) inside the block; one 4-word
+  // vector, as loaded, so the prefetch stages keep it in one register tuple
+  bi4 cj;
   double f[MAXD][C * KF];
   double dv[C * KF];   // pivot (backward sweeps)
   el<C, K> ye[MAXD];   // words of external dependencies (raw)
@@ -568,11 +577,12 @@ template <int C, int K, int KF, int MAXD> struct RowPre {
 
 // The buffers of one sweep.
 struct SweepBufs {
-  __amdgpu_buffer_rsrc_t order, nd, col, val, dval, out;
+  __amdgpu_buffer_rsrc_t order, nd, slot, col, val, dval, out;
 };
 
-// Stage 1 (D levels ahead): row index, dependency count, the first ELLW
-// dependency columns and factor values, and the pivot, by position.
+// Stage 1 (D levels ahead): row index, dependency count, LDS slot, the
+// first ELLW flat dependency slots and factor values, and the pivot, by
+// position.
 template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
 __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_t pos, bool valid,
                                                const SweepBufs &B) {
@@ -582,12 +592,9 @@ __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_
   const uint32_t p4 = valid ? uint32_t(pos) * 4u : BUF_OOB;
   r.i = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.order, int(p4), 0, 0));
   r.nd = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.nd, int(p4), 0, 0));
-  const bu4 cj = __builtin_amdgcn_raw_buffer_load_b128(
-      B.col, int(valid ? uint32_t(pos) * 4u * ELLW : BUF_OOB), 0, 0);
-  r.cj[0] = int32_t(cj.x);
-  r.cj[1] = int32_t(cj.y);
-  r.cj[2] = int32_t(cj.z);
-  r.cj[3] = int32_t(cj.w);
+  r.slot = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.slot, int(p4), 0, 0));
+  r.cj = __builtin_bit_cast(bi4, __builtin_amdgcn_raw_buffer_load_b128(
+                                     B.col, int(valid ? uint32_t(pos) * 4u * ELLW : BUF_OOB), 0, 0));
   const uint32_t fo = valid ? uint32_t(pos) * uint32_t(ELLW * C * KF * 8) : BUF_OOB;
 #pragma unroll
   for (int d = 0; d < MAXD; ++d)
@@ -607,19 +614,17 @@ __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_
 }
 
 template <int C, int K, int KF, int MAXD>
-__device__ __forceinline__ bool dep_external(const RowPre<C, K, KF, MAXD> &r, int d, int32_t r0,
-                                             int32_t r1) {
-  return r.valid && d < r.nd && !(r.cj[d] >= r0 && r.cj[d] < r1);
+__device__ __forceinline__ bool dep_external(const RowPre<C, K, KF, MAXD> &r, int d) {
+  return r.valid && d < r.nd && r.cj[d] >= 0;
 }
 
 // Stage 2 (X levels ahead): the words of dependencies outside the block.
 template <int C, int K, int KF, int MAXD>
-__device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const SweepBufs &B,
-                                              int32_t r0, int32_t r1) {
+__device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const SweepBufs &B) {
   constexpr int E = C * K;
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
-    const uint32_t o = dep_external<C, K, KF, MAXD>(r, d, r0, r1)
+    const uint32_t o = dep_external<C, K, KF, MAXD>(r, d)
                            ? uint32_t(r.cj[d]) * uint32_t(E * 8) : BUF_OOB;
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -632,16 +637,18 @@ __device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const S
 // Finish one row: acc = rhs_i (staged in the row's LDS slot) minus the
 // products in ascending column order, divided by the pivot when DIV; the
 // result goes to the row's LDS slot and to out.  A lane without a row uses
-// LDS slot r1 - r0 and an out-of-range store.
+// the spare LDS slot `spare` and an out-of-range store.  Dependencies past
+// the ELLW flat slots come from the CSR arrays; the host allows them only
+// for blocks of one range [r0, r1), where row j sits in slot j - r0.
 template <int C, int K, int KF, bool DIV, bool CONJ, int MAXD>
 __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int32_t *__restrict__ ptr,
                                            const int32_t *__restrict__ col,
                                            const double *__restrict__ val, double *out,
                                            const SweepBufs &B, double *lds, int32_t r0,
-                                           int32_t r1, int32_t *abort_flag) {
+                                           int32_t r1, int32_t spare, int32_t *abort_flag) {
   constexpr int E = C * K;
   const int32_t pe = r.valid ? r.nd : 0;
-  const int32_t slot = r.valid ? r.i - r0 : r1 - r0;
+  const int32_t slot = r.valid ? r.slot : spare;
   el<C, K> acc = el_load<C, K>(lds + size_t(slot) * E);
   {
     el<C, K> yv[MAXD];
@@ -649,8 +656,8 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
 #pragma unroll
     for (int d = 0; d < MAXD; ++d) {
       const int32_t j = r.cj[d];
-      const bool in = j >= r0 && j < r1;
-      yv[d] = el_load<C, K>(lds + size_t(d < pe && in ? j - r0 : r1 - r0) * E);
+      const bool in = j < 0;
+      yv[d] = el_load<C, K>(lds + size_t(d < pe && in ? -j - 1 : spare) * E);
       if (d < pe && !in) {
         yv[d] = r.ye[d];
 #pragma unroll
@@ -663,7 +670,7 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
     if (!ok) {
 #pragma unroll
       for (int d = 0; d < MAXD; ++d)
-        if (dep_external<C, K, KF, MAXD>(r, d, r0, r1))
+        if (dep_external<C, K, KF, MAXD>(r, d))
           wait_load<C, K>(out + size_t(r.cj[d]) * E, yv[d], abort_flag);
     }
 #pragma unroll
@@ -708,14 +715,16 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Prefetch depth (local levels) of the blocked sweep's row data.
-template <int E> constexpr int trsv_depth() { return E <= 2 ? 4 : 2; }
+template <int E> constexpr int trsv_depth() { return E <= 2 ? 6 : 4; }
+template <int E> constexpr int trsv_lead() { return E <= 2 ? 3 : 2; }
 
-// Blocked sweep: a workgroup takes the next block of consecutive rows (in
-// sweep order), stages its rhs in LDS and walks the block's local levels
-// (each at most BLOCK rows: one per lane), separated by LDS-only barriers.
-// Values of other blocks are read from out with the sentinel-checked
-// wait.  LDS: (rows per block + 1) * C * K doubles, the last slot for
-// lanes without a row.  The buffers' byte sizes must stay below 2^31
+// Blocked sweep: a workgroup takes the next block (in sweep order: nrange
+// ranges of up to `width` rows starting `period` rows apart, first range
+// [r0, r1) from blk_r; one range of consecutive rows when nrange = 1),
+// stages its rhs in LDS and walks the block's local levels (each at most
+// BLOCK rows: one per lane), separated by LDS-only barriers.  Values of
+// other blocks are read from out with the sentinel-checked wait.  LDS:
+// (spare + 1) * C * K doubles, slot `spare` for lanes without a row.  The buffers' byte sizes must stay below 2^31
 // (the host picks the level schedule otherwise).  About one workgroup per
 // CU (the LDS block decides), so the register budget may grow to keep the
 // prefetch stages out of scratch.
@@ -726,7 +735,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
     const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
     const int32_t *__restrict__ ell_nd, const int32_t *__restrict__ ell_col,
-    const double *__restrict__ ell_val, const double *__restrict__ rhs, double *out,
+    const int32_t *__restrict__ ell_slot, const double *__restrict__ ell_val, int64_t period,
+    int32_t nrange, int32_t width, int32_t spare, const double *__restrict__ rhs, double *out,
     int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
   if (done && *done) return;
   extern __shared__ double lds[];
@@ -734,12 +744,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   constexpr int E = C * K;
   constexpr int MAXD = ELLW;
   constexpr int D = trsv_depth<E>();
-  constexpr int X = D - 1;  // levels ahead at which external values are requested
+  constexpr int X = trsv_lead<E>();  // levels ahead at which external values are requested
   using RP = RowPre<C, K, KF, MAXD>;
   const int32_t tid = threadIdx.x;
   SweepBufs B;
   B.order = buf_rsrc(order, n * 4);
   B.nd = buf_rsrc(ell_nd, n * 4);
+  B.slot = buf_rsrc(ell_slot, n * 4);
   B.col = buf_rsrc(ell_col, n * 4 * ELLW);
   B.val = buf_rsrc(ell_val, n * ELLW * C * KF * 8);
   B.dval = buf_rsrc(DIV ? dval : ell_val, DIV ? n * C * KF * 8 : 0);
@@ -752,27 +763,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     if (b >= nblk) break;
     const int32_t r0 = blk_r[2 * b], r1 = blk_r[2 * b + 1];
     const int32_t l0 = blk_lev[b], l1 = blk_lev[b + 1];
-    // stage the block's right-hand side into LDS (contiguous rows)
-    for (int64_t w = tid; w < int64_t(r1 - r0) * E; w += BLOCK) lds[w] = rhs[size_t(r0) * E + w];
+    // stage the block's right-hand side into LDS: range k (rows
+    // [r0 + k * period, + r1 - r0), clipped to n) fills slots k * width on
+    for (int32_t k = 0; k < nrange; ++k) {
+      const int64_t a = r0 + int64_t(k) * period;
+      if (a >= n) break;
+      const int64_t words = (min(a + int64_t(r1 - r0), n) - a) * E;
+      for (int64_t w = tid; w < words; w += BLOCK)
+        lds[int64_t(k) * width * E + w] = rhs[size_t(a) * E + w];
+    }
     // row data of local level l (empty past the block's last level)
     auto meta = [&](RP &r, int32_t l) {
       const int32_t pb = loc_pos[min(l, l1)], pe = loc_pos[min(l + 1, l1)];
       row_fetch_meta<C, K, KF, DIV, CONJ, MAXD>(r, pb + tid, pb + tid < pe, B);
     };
+    // prologue in the steady state's issue pattern (the external values of
+    // level l + X, then the row data of level l + D), so the compiler's
+    // count of loads in flight at the loop head is the same on both paths
+    // and its waits stay partial
     RP st[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) meta(st[u], l0 + u);
-    __syncthreads();
+    for (int u = 0; u < D - X; ++u) meta(st[u], l0 + u);
 #pragma unroll
-    for (int u = 0; u < X; ++u) row_fetch_ext<C, K, KF, MAXD>(st[u], B, r0, r1);
+    for (int u = D - X; u < D; ++u) {
+      row_fetch_ext<C, K, KF, MAXD>(st[u - (D - X)], B);
+      meta(st[u], l0 + u);
+    }
+    __syncthreads();
     // one local level: finish `now`; then request the external values of
     // level l+X (slot `ext`, whose indices arrived D-X stages ago) and
     // refill `now` with the row data of level l+D
     auto stage = [&](RP &now, RP &ext, int32_t l) {
-      row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, out, B, lds, r0, r1,
+      row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, out, B, lds, r0, r1, spare,
                                             abort_flag);
       lds_barrier();
-      row_fetch_ext<C, K, KF, MAXD>(ext, B, r0, r1);
+      row_fetch_ext<C, K, KF, MAXD>(ext, B);
       meta(now, l + D);
     };
     for (int32_t lv = l0; lv < l1; lv += D) {

@@ -105,7 +105,8 @@ static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
   hipLaunchKernelGGL(plan_fill, dim3(g), dim3(BLOCK), 0, s, n, P.order, rp, ci,
                      tr ? (const int32_t *)M.t_src : nullptr, lower, (const int32_t *)P.ptr, P.col,
                      P.src, ell ? P.ell_nd : nullptr, ell ? P.ell_col : nullptr,
-                     ell ? P.ell_src : nullptr, (const int32_t *)M.diag, P.div ? P.dsrc : nullptr);
+                     ell ? P.ell_src : nullptr, ell ? P.ell_slot : nullptr, P.geom,
+                     (const int32_t *)M.diag, P.div ? P.dsrc : nullptr);
   MPK_HIP(hipGetLastError());
   int32_t tot = 0;
   MPK_HIP(hipMemcpyAsync(&tot, P.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -277,7 +278,8 @@ static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
     const size_t lds = size_t(P.blk_rows + 1) * C * K * sizeof(double);
     hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK),
                        lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
-                       P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_val, rhs, out, P.sync,
+                       P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot, P.ell_val,
+                       P.geom.P, P.geom.t, P.geom.w, P.blk_rows, rhs, out, P.sync,
                        abort_flag, done);
     return;
   }

@@ -124,6 +124,47 @@ def test_ilu0_apply_bitwise(mpk, orc, name, kf, K):
     assert np.array_equal(zh, zho)
 
 
+def complex_grid2d(m, seed):
+    """A complex matrix on the 5-point pattern of an m x m grid (diagonally
+    dominant): the pattern of config1 with random complex values."""
+    p = W.config1(m)
+    rng = np.random.default_rng(seed)
+    val = np.zeros((len(p.col_idx), 2))
+    val[:, 0] = p.val
+    val[:, 1] = 0.3 * rng.uniform(-1, 1, len(p.col_idx))
+    return p.row_ptr, p.col_idx, val
+
+
+@pytest.mark.parametrize("shape", ["conv3d_20", "conv2d_150", "cplx2d_70"])
+@pytest.mark.parametrize("rows", [256, 1024])
+@pytest.mark.parametrize("kf,K", [(1, 2), (2, 3), (1, 4)])
+def test_ilu0_apply_deep_blocks_bitwise(mpk, orc, monkeypatch, shape, rows, kf, K):
+    """Blocked sweeps with blocks several grid planes (or lines) deep: small
+    blocks force many of them, including short ones at the grid's end, on
+    3D and 2D grids and a complex system; all four sweeps (L, U and the
+    adjoint pair) against the oracle, element by element."""
+    monkeypatch.setenv("MPK_TRSV_BLOCK_ROWS", str(rows))
+    if shape == "conv3d_20":
+        p = W.config2(20)
+        rp, ci, val, C = p.row_ptr, p.col_idx, p.val, 1
+    elif shape == "conv2d_150":
+        p = W.config1(150)
+        rp, ci, val, C = p.row_ptr, p.col_idx, p.val, 1
+    else:
+        rp, ci, val = complex_grid2d(70, 5)
+        C = 2
+    n = len(rp) - 1
+    A = mpk.Csr(rp, ci, val)
+    M = mpk.ilu0_factor(A, kf, adjoint=True)
+    st, bad, f = orc.ilu0(rp, ci, val, C, kf)
+    assert st == 0
+    r = rand_vec(np.random.default_rng(7 * K + kf + rows), n, C, K)
+    z = host(mpk.ilu0_apply(M, dev(r)))
+    assert np.array_equal(z, orc.ilu0_apply(rp, ci, f, r))
+    zh = host(mpk.ilu0_apply(M, dev(r), conj_trans=True))
+    assert np.array_equal(zh, orc.ilu0_apply(rp, ci, f, r, conj_trans=True))
+
+
 @pytest.mark.parametrize("C,K", [(1, 1), (1, 2), (1, 4), (2, 2), (2, 3)])
 @pytest.mark.parametrize("n", [1, 255, 256, 257, 100003])
 def test_dot_within_bound(mpk, orc, C, K, n):

@@ -344,7 +344,7 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
   // order.  Block b's positions start after those of the blocks processed
   // before it (in the backward direction the first one is the short tail).
   std::vector<std::vector<int32_t>> bpos(size_t(p.nblk));
-  std::vector<int32_t> bbase(size_t(p.nblk) + 1, 0);
+  std::vector<int32_t> bbase(size_t(p.nblk) + 1, 0), bwide(size_t(p.nblk), 0);
   for (int32_t b = 0; b < p.nblk; ++b) {
     const int64_t id = forward ? b : p.nblk - 1 - b;
     int64_t r0, wb, rows = 0;
@@ -391,8 +391,12 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
     // a local level wider than a workgroup is cut into pieces of at most
     // BLOCK rows (its rows are independent), so a lane owns one row
     std::vector<int32_t> &bp = bpos[size_t(b)];
-    for (int32_t l = 0; l < nl; ++l)
+    int32_t widest = 0;
+    for (int32_t l = 0; l < nl; ++l) {
+      widest = std::max(widest, std::min(BLOCK, cnt[l + 1] - cnt[l]));
       for (int32_t q = cnt[l]; q < cnt[l + 1]; q += BLOCK) bp.push_back(base + q);
+    }
+    bwide[size_t(b)] = widest;
     each_row([&](int64_t i) { p.order[base + cnt[loc[SLOT(i)]]++] = int32_t(i); });
   };
   {
@@ -406,6 +410,7 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
     work(0);
     for (auto &x : th) x.join();
   }
+  p.max_piece = p.nblk ? *std::max_element(bwide.begin(), bwide.end()) : 0;
   for (int32_t b = 0; b < p.nblk; ++b) {
     p.blk_lev[b] = int32_t(p.loc_pos.size());
     p.loc_pos.insert(p.loc_pos.end(), bpos[size_t(b)].begin(), bpos[size_t(b)].end());
@@ -455,6 +460,7 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
   p.mode = hp.mode;
   p.nblk = hp.nblk;
   p.blk_rows = hp.blk_rows;
+  p.max_piece = hp.max_piece;
   p.geom = hp.geom;
   MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * p.n, hipMemcpyHostToDevice, s));
   (void)n;

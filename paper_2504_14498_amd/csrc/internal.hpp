@@ -116,6 +116,7 @@ struct Plan {
   int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
   int32_t kmax = 4;            // largest vector precision the blocks are sized for
   int32_t blk_rows = 0;        // LDS slots per block (t * w)
+  int32_t max_piece = 0;       // rows of the widest local level piece
   BlockGeom geom;              // block shape
   int32_t *blk_r = nullptr;    // [2*nblk] first range [r0, r1) of each block
   int32_t *blk_lev = nullptr;  // [nblk+1] first local level of each block
@@ -236,7 +237,7 @@ void host_diag(const HostCsr &h, std::vector<int32_t> &diag);
 struct HostPlan {
   std::vector<int32_t> order, ptr, col, src, dsrc, seg, seg_level, levptr;
   int32_t nlev = 0;
-  int32_t mode = 0, nblk = 0, blk_rows = 0;
+  int32_t mode = 0, nblk = 0, blk_rows = 0, max_piece = 0;
   BlockGeom geom;
   std::vector<int32_t> blk_r, blk_lev, loc_pos;
   std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)

@@ -573,11 +573,12 @@ template <int C, int K, int KF, int MAXD> struct RowPre {
   double f[MAXD][C * KF];
   double dv[C * KF];   // pivot (backward sweeps)
   el<C, K> ye[MAXD];   // words of external dependencies (raw)
+  el<C, K> rh;         // the row's right-hand side
 };
 
 // The buffers of one sweep.
 struct SweepBufs {
-  __amdgpu_buffer_rsrc_t order, nd, slot, col, val, dval, out;
+  __amdgpu_buffer_rsrc_t order, nd, slot, col, val, dval, rhs, out;
 };
 
 // Stage 1 (D levels ahead): row index, dependency count, LDS slot, the
@@ -618,10 +619,18 @@ __device__ __forceinline__ bool dep_external(const RowPre<C, K, KF, MAXD> &r, in
   return r.valid && d < r.nd && r.cj[d] >= 0;
 }
 
-// Stage 2 (X levels ahead): the words of dependencies outside the block.
+// Stage 2 (X levels ahead): the row's right-hand side and the words of
+// dependencies outside the block.
 template <int C, int K, int KF, int MAXD>
 __device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const SweepBufs &B) {
   constexpr int E = C * K;
+  {
+    const uint32_t o = r.valid ? uint32_t(r.i) * uint32_t(E * 8) : BUF_OOB;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int k = 0; k < K; ++k) r.rh.c[c].v[k] = buf_ld<0>(B.rhs, o + uint32_t((c * K + k) * 8));
+  }
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
     const uint32_t o = dep_external<C, K, KF, MAXD>(r, d)
@@ -634,7 +643,45 @@ __device__ __forceinline__ void row_fetch_ext(RowPre<C, K, KF, MAXD> &r, const S
   }
 }
 
-// Finish one row: acc = rhs_i (staged in the row's LDS slot) minus the
+// Re-polls the external dependencies whose prefetched words still hold the
+// sentinel, all of them in one bounded loop (one copy of the slow path per
+// level keeps the unrolled level loop small), until every word is written.
+template <int C, int K, int KF, int MAXD>
+__device__ __forceinline__ void wait_ext(RowPre<C, K, KF, MAXD> &r, int32_t pe, const SweepBufs &B,
+                                      int32_t *abort_flag) {
+  constexpr int E = C * K;
+  for (int it = 0;; ++it) {
+    bool miss = false;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      bool hit = false;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          hit = hit | (__builtin_bit_cast(uint64_t, r.ye[d].c[c].v[k]) == SENTINEL);
+      const bool m = (d < pe) & (r.cj[d] >= 0) & hit;
+      miss = miss | m;
+      const uint32_t o = m ? uint32_t(r.cj[d]) * uint32_t(E * 8) : BUF_OOB;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double v = buf_ld<BUF_AGENT>(B.out, o + uint32_t((c * K + k) * 8));
+          r.ye[d].c[c].v[k] = m ? v : r.ye[d].c[c].v[k];
+        }
+    }
+    if (!miss) return;
+    if ((it & 63) == 63 && ld_agent_i(abort_flag)) return;
+    if (it >= SPIN_LIMIT) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Finish one row: acc = rhs_i (prefetched with the external values) minus the
 // products in ascending column order, divided by the pivot when DIV; the
 // result goes to the row's LDS slot and to out.  A lane without a row uses
 // the spare LDS slot `spare` and an out-of-range store.  Dependencies past
@@ -649,33 +696,41 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
   constexpr int E = C * K;
   const int32_t pe = r.valid ? r.nd : 0;
   const int32_t slot = r.valid ? r.slot : spare;
-  el<C, K> acc = el_load<C, K>(lds + size_t(slot) * E);
+  el<C, K> acc = r.rh;
   {
-    el<C, K> yv[MAXD];
-    bool ok = true;
+    // in-block values from LDS (the spare slot for other slots), kept apart
+    // from the prefetched external words: overwriting a register that an
+    // LDS read still fills would serialise the reads
+    el<C, K> yl[MAXD];
 #pragma unroll
     for (int d = 0; d < MAXD; ++d) {
       const int32_t j = r.cj[d];
-      const bool in = j < 0;
-      yv[d] = el_load<C, K>(lds + size_t(d < pe && in ? -j - 1 : spare) * E);
-      if (d < pe && !in) {
-        yv[d] = r.ye[d];
+      yl[d] = el_load<C, K>(lds + size_t(d < pe && j < 0 ? -j - 1 : spare) * E);
+    }
+    // (bitwise operators: no short-circuit branches)
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      bool hit = false;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          hit = hit | (__builtin_bit_cast(uint64_t, r.ye[d].c[c].v[k]) == SENTINEL);
+      bad = bad | ((d < pe) & (r.cj[d] >= 0) & hit);
+    }
+    if (bad) wait_ext<C, K, KF, MAXD>(r, pe, B, abort_flag);
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d)
+      if (d < pe) {
+        el<C, K> y;
+        const bool ext = r.cj[d] >= 0;
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-          for (int k = 0; k < K; ++k)
-            ok = ok && __builtin_bit_cast(uint64_t, yv[d].c[c].v[k]) != SENTINEL;
+          for (int k = 0; k < K; ++k) y.c[c].v[k] = ext ? r.ye[d].c[c].v[k] : yl[d].c[c].v[k];
+        acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], y));
       }
-    }
-    if (!ok) {
-#pragma unroll
-      for (int d = 0; d < MAXD; ++d)
-        if (dep_external<C, K, KF, MAXD>(r, d))
-          wait_load<C, K>(out + size_t(r.cj[d]) * E, yv[d], abort_flag);
-    }
-#pragma unroll
-    for (int d = 0; d < MAXD; ++d)
-      if (d < pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(r.f[d], yv[d]));
   }
   // rows with more than MAXD dependencies: the rest from the CSR arrays
   if (pe > MAXD) {
@@ -718,25 +773,31 @@ __device__ __forceinline__ void lds_barrier() {
 template <int E> constexpr int trsv_depth() { return E <= 2 ? 6 : 4; }
 template <int E> constexpr int trsv_lead() { return E <= 2 ? 3 : 2; }
 
-// Blocked sweep: a workgroup takes the next block (in sweep order: nrange
-// ranges of up to `width` rows starting `period` rows apart, first range
-// [r0, r1) from blk_r; one range of consecutive rows when nrange = 1),
-// stages its rhs in LDS and walks the block's local levels (each at most
-// BLOCK rows: one per lane), separated by LDS-only barriers.  Values of
-// other blocks are read from out with the sentinel-checked wait.  LDS:
-// (spare + 1) * C * K doubles, slot `spare` for lanes without a row.  The buffers' byte sizes must stay below 2^31
-// (the host picks the level schedule otherwise).  About one workgroup per
-// CU (the LDS block decides), so the register budget may grow to keep the
-// prefetch stages out of scratch.
-template <int C, int K, int KF, bool DIV, bool CONJ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_blocked(
+// Blocked sweep: a workgroup takes the next block (in sweep order; its
+// rows and their LDS slots come from the plan, see BlockGeom) and walks the
+// block's local levels (each at most NT rows: one per lane), separated by
+// LDS-only barriers.  A row's right-hand side is prefetched with its
+// external values; in-block results are kept in LDS for the rows that need
+// them, and values of other blocks are read from out with the
+// sentinel-checked wait.  blk_r holds the first range [r0, r1) of each
+// block, used only by rows with more than ELLW dependencies (the host
+// allows those only in blocks of one range).  LDS: (spare + 1) * C * K
+// doubles, slot `spare` for lanes without a row.  The buffers' byte sizes
+// must stay below 2^31 (the host picks the level schedule otherwise).
+// About one workgroup per CU (the LDS block decides), so the register
+// budget may grow to keep the prefetch stages out of scratch.
+// NT threads per workgroup: BLOCK, or one wavefront when no local level
+// piece of the plan has more than WAVE rows (no idle wavefronts then
+// issue their out-of-range loads beside the working one).
+template <int C, int K, int KF, bool DIV, bool CONJ, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_blocked(
     int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
     const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
     const int32_t *__restrict__ ell_nd, const int32_t *__restrict__ ell_col,
-    const int32_t *__restrict__ ell_slot, const double *__restrict__ ell_val, int64_t period,
-    int32_t nrange, int32_t width, int32_t spare, const double *__restrict__ rhs, double *out,
+    const int32_t *__restrict__ ell_slot, const double *__restrict__ ell_val, int32_t spare,
+    const double *__restrict__ rhs, double *out,
     int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
   if (done && *done) return;
   extern __shared__ double lds[];
@@ -754,6 +815,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   B.col = buf_rsrc(ell_col, n * 4 * ELLW);
   B.val = buf_rsrc(ell_val, n * ELLW * C * KF * 8);
   B.dval = buf_rsrc(DIV ? dval : ell_val, DIV ? n * C * KF * 8 : 0);
+  B.rhs = buf_rsrc(rhs, n * E * 8);
   B.out = buf_rsrc(out, n * E * 8);
   for (;;) {
     if (tid == 0) cur = atomicAdd(ticket, 1);
@@ -763,15 +825,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     if (b >= nblk) break;
     const int32_t r0 = blk_r[2 * b], r1 = blk_r[2 * b + 1];
     const int32_t l0 = blk_lev[b], l1 = blk_lev[b + 1];
-    // stage the block's right-hand side into LDS: range k (rows
-    // [r0 + k * period, + r1 - r0), clipped to n) fills slots k * width on
-    for (int32_t k = 0; k < nrange; ++k) {
-      const int64_t a = r0 + int64_t(k) * period;
-      if (a >= n) break;
-      const int64_t words = (min(a + int64_t(r1 - r0), n) - a) * E;
-      for (int64_t w = tid; w < words; w += BLOCK)
-        lds[int64_t(k) * width * E + w] = rhs[size_t(a) * E + w];
-    }
     // row data of local level l (empty past the block's last level)
     auto meta = [&](RP &r, int32_t l) {
       const int32_t pb = loc_pos[min(l, l1)], pe = loc_pos[min(l + 1, l1)];

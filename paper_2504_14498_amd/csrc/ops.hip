@@ -276,11 +276,22 @@ static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
     }();
     const unsigned grid = unsigned(std::min<int64_t>(P.nblk, bcap));
     const size_t lds = size_t(P.blk_rows + 1) * C * K * sizeof(double);
-    hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ>), dim3(grid ? grid : 1), dim3(BLOCK),
-                       lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r, P.blk_lev,
-                       P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot, P.ell_val,
-                       P.geom.P, P.geom.t, P.geom.w, P.blk_rows, rhs, out, P.sync,
-                       abort_flag, done);
+    static const bool one_wave = [] {
+      const char *e = getenv("MPK_TRSV_ONE_WAVE");
+      return !e || e[0] != '0';
+    }();
+    if (one_wave && P.max_piece <= WAVE)
+      hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, WAVE>), dim3(grid ? grid : 1),
+                         dim3(WAVE), lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r,
+                         P.blk_lev, P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot,
+                         P.ell_val, P.blk_rows, rhs, out, P.sync,
+                         abort_flag, done);
+    else
+      hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, BLOCK>), dim3(grid ? grid : 1),
+                         dim3(BLOCK), lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r,
+                         P.blk_lev, P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot,
+                         P.ell_val, P.blk_rows, rhs, out, P.sync,
+                         abort_flag, done);
     return;
   }
   static const int64_t cap = [] {

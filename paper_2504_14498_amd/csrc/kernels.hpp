@@ -770,8 +770,8 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Prefetch depth (local levels) of the blocked sweep's row data.
-template <int E> constexpr int trsv_depth() { return E <= 2 ? 6 : 4; }
-template <int E> constexpr int trsv_lead() { return E <= 2 ? 3 : 2; }
+template <int E> constexpr int trsv_depth() { return E <= 2 ? 6 : 3; }
+template <int E> constexpr int trsv_lead() { return E <= 2 ? 2 : 1; }
 
 // Blocked sweep: a workgroup takes the next block (in sweep order; its
 // rows and their LDS slots come from the plan, see BlockGeom) and walks the

@@ -217,7 +217,8 @@ static BlockGeom deep_geom(const DepView &dv, int64_t n, int cap) {
   return g;
 }
 
-void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
+void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
+                       HostPlan &p) {
   const int64_t n = h.n;
   const HostCsr &g = (kind >= 2) ? *ht : h;
   const DepView dv{g.rp, g.ci, kind == 0 || kind == 2};
@@ -264,8 +265,16 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
         p.seg_level.push_back(l);
       }
     p.seg.push_back(int32_t(n));
-    return;
   }
+}
+
+void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
+                       HostPlan &p) {
+  if (p.mode != 1) return;
+  const int64_t n = h.n;
+  const HostCsr &g = (kind >= 2) ? *ht : h;
+  const DepView dv{g.rp, g.ci, kind == 0 || kind == 2};
+  const bool forward = (kind == 0 || kind == 2);
   // blocked schedule: blocks (plain row ranges or a few periods deep, see
   // deep_geom) taken in the sweep's direction, each ordered by its local
   // (block-internal) levels
@@ -423,6 +432,11 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
   p.seg_level.assign(1, 0);
 }
 
+void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
+  build_plan_levels(h, ht, kind, blk_rows, p);
+  build_plan_blocks(h, ht, kind, blk_rows, p);
+}
+
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out) {
   Plan tmp;
   Plan &p = out ? *out : tmp;
@@ -442,7 +456,7 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
   p.sync = b.take<int32_t>(64);
   p.ell_nd = b.take<int32_t>(size_t(n));
   p.ell_col = b.take<int32_t>(size_t(n) * ELLW);
-  p.ell_slot = b.take<int32_t>(size_t(n));
+  p.ell_meta = b.take<int32_t>(size_t(n) * 4);
   p.ell_src = b.take<int32_t>(size_t(n) * ELLW);
   p.ell_val = b.take<double>(size_t(n) * ELLW * C * KF);
   p.blk_r = b.take<int32_t>(2 * size_t(n) + 2);

@@ -125,7 +125,7 @@ struct Plan {
   // dependencies of the row at position pos live at [pos * ELLW + d]
   int32_t *ell_nd = nullptr;   // [n] dependencies of each position
   int32_t *ell_col = nullptr;  // [n * ELLW] column j, or -(slot + 1) if j is in the row's block
-  int32_t *ell_slot = nullptr; // [n] LDS slot of the row at each position
+  int32_t *ell_meta = nullptr; // [n * 4] row, dependency count, LDS slot, 0 (blocked sweeps)
   int32_t *ell_src = nullptr;  // [n * ELLW] value source in A's pattern (-1 pad)
   double *ell_val = nullptr;   // [n * ELLW * C * KF]
   std::vector<int32_t> h_blk;  // host copies kept alive for the uploads
@@ -247,6 +247,13 @@ struct HostPlan {
 // 3 = L^H (columns of the strict lower part, backward).
 // ht: the transposed pattern (needed for kinds 2 and 3 only).
 void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p);
+// The two halves of build_plan: global levels, the schedule choice, the
+// factorisation order (kind 0) and the level schedule; then the blocked
+// schedule when it was chosen.
+void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
+                       HostPlan &p);
+void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
+                       HostPlan &p);
 int default_block_rows(int C, int kmax);
 size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b, Plan *out);
 int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);

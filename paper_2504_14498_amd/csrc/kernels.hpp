@@ -253,20 +253,25 @@ static __global__ void scan_add(int64_t n, int32_t *out, const int32_t *__restri
 // A's pattern; srcmap maps the rows of A^T back to A) in ascending column
 // order, the flat ELLW slots of the blocked sweeps, and the pivot position.
 // A flat slot holds the column j of a dependency in another block, or
-// -(LDS slot of j + 1) for one in the row's own block (geometry G); the
-// row's own LDS slot goes to ell_slot.
+// -(LDS slot of j + 1) for one in the row's own block (geometry G); each
+// position's row, dependency count and own LDS slot go to one 16-byte
+// record of ell_meta, fetched with a single load.
 static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                  const int32_t *__restrict__ srcmap, int lower,
                                  const int32_t *__restrict__ ptr, int32_t *col, int32_t *src,
                                  int32_t *ell_nd, int32_t *ell_col, int32_t *ell_src,
-                                 int32_t *ell_slot, BlockGeom G,
+                                 int32_t *ell_meta, BlockGeom G,
                                  const int32_t *__restrict__ diag, int32_t *dsrc) {
   const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   if (pos >= n) return;
   const int32_t i = order[pos];
   const int64_t bi = ell_nd ? G.block(i) : 0;
-  if (ell_nd) ell_slot[pos] = G.slot(i);
+  if (ell_nd) {
+    ell_meta[pos * 4] = i;
+    ell_meta[pos * 4 + 2] = G.slot(i);
+    ell_meta[pos * 4 + 3] = 0;
+  }
   int32_t o = ptr[pos], d = 0;
   for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
     const int32_t j = ci[q];
@@ -284,6 +289,7 @@ static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
   }
   if (ell_nd) {
     ell_nd[pos] = d;
+    ell_meta[pos * 4 + 1] = d;
     for (int32_t k = d; k < ELLW; ++k) {
       ell_col[pos * ELLW + k] = 0;
       ell_src[pos * ELLW + k] = -1;
@@ -578,7 +584,7 @@ template <int C, int K, int KF, int MAXD> struct RowPre {
 
 // The buffers of one sweep.
 struct SweepBufs {
-  __amdgpu_buffer_rsrc_t order, nd, slot, col, val, dval, rhs, out;
+  __amdgpu_buffer_rsrc_t meta, col, val, dval, rhs, out;
 };
 
 // Stage 1 (D levels ahead): row index, dependency count, LDS slot, the
@@ -590,10 +596,11 @@ __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_
   static_assert(MAXD == ELLW, "one slot per flat dependency");
   r.pos = pos;
   r.valid = valid;
-  const uint32_t p4 = valid ? uint32_t(pos) * 4u : BUF_OOB;
-  r.i = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.order, int(p4), 0, 0));
-  r.nd = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.nd, int(p4), 0, 0));
-  r.slot = int32_t(__builtin_amdgcn_raw_buffer_load_b32(B.slot, int(p4), 0, 0));
+  const bu4 m = __builtin_amdgcn_raw_buffer_load_b128(
+      B.meta, int(valid ? uint32_t(pos) * 16u : BUF_OOB), 0, 0);
+  r.i = int32_t(m.x);
+  r.nd = int32_t(m.y);
+  r.slot = int32_t(m.z);
   r.cj = __builtin_bit_cast(bi4, __builtin_amdgcn_raw_buffer_load_b128(
                                      B.col, int(valid ? uint32_t(pos) * 4u * ELLW : BUF_OOB), 0, 0));
   const uint32_t fo = valid ? uint32_t(pos) * uint32_t(ELLW * C * KF * 8) : BUF_OOB;
@@ -765,8 +772,14 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
 // (a full __syncthreads would drain the prefetch pipeline at every level).
 // The asm statement also keeps the compiler from moving memory accesses
 // across it.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+template <int NT> __device__ __forceinline__ void lds_barrier() {
+  if constexpr (NT == WAVE) {
+    // one wavefront: its LDS operations execute in program order, so a
+    // later read sees an earlier write; only the compiler is fenced
+    asm volatile("" ::: "memory");
+  } else {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  }
 }
 
 // Prefetch depth (local levels) of the blocked sweep's row data.
@@ -791,12 +804,11 @@ template <int E> constexpr int trsv_lead() { return E <= 2 ? 2 : 1; }
 // issue their out-of-range loads beside the working one).
 template <int C, int K, int KF, bool DIV, bool CONJ, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_blocked(
-    int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ ptr,
-    const int32_t *__restrict__ col, const double *__restrict__ val,
-    const double *__restrict__ dval, const int32_t *__restrict__ blk_r,
-    const int32_t *__restrict__ blk_lev, const int32_t *__restrict__ loc_pos, int32_t nblk,
-    const int32_t *__restrict__ ell_nd, const int32_t *__restrict__ ell_col,
-    const int32_t *__restrict__ ell_slot, const double *__restrict__ ell_val, int32_t spare,
+    int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ dval,
+    const int32_t *__restrict__ blk_r, const int32_t *__restrict__ blk_lev,
+    const int32_t *__restrict__ loc_pos, int32_t nblk, const int32_t *__restrict__ ell_col,
+    const int32_t *__restrict__ ell_meta, const double *__restrict__ ell_val, int32_t spare,
     const double *__restrict__ rhs, double *out,
     int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
   if (done && *done) return;
@@ -809,9 +821,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
   using RP = RowPre<C, K, KF, MAXD>;
   const int32_t tid = threadIdx.x;
   SweepBufs B;
-  B.order = buf_rsrc(order, n * 4);
-  B.nd = buf_rsrc(ell_nd, n * 4);
-  B.slot = buf_rsrc(ell_slot, n * 4);
+  B.meta = buf_rsrc(ell_meta, n * 16);
   B.col = buf_rsrc(ell_col, n * 4 * ELLW);
   B.val = buf_rsrc(ell_val, n * ELLW * C * KF * 8);
   B.dval = buf_rsrc(DIV ? dval : ell_val, DIV ? n * C * KF * 8 : 0);
@@ -849,7 +859,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     auto stage = [&](RP &now, RP &ext, int32_t l) {
       row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, out, B, lds, r0, r1, spare,
                                             abort_flag);
-      lds_barrier();
+      lds_barrier<NT>();
       row_fetch_ext<C, K, KF, MAXD>(ext, B);
       meta(now, l + D);
     };

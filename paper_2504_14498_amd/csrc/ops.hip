@@ -105,7 +105,7 @@ static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
   hipLaunchKernelGGL(plan_fill, dim3(g), dim3(BLOCK), 0, s, n, P.order, rp, ci,
                      tr ? (const int32_t *)M.t_src : nullptr, lower, (const int32_t *)P.ptr, P.col,
                      P.src, ell ? P.ell_nd : nullptr, ell ? P.ell_col : nullptr,
-                     ell ? P.ell_src : nullptr, ell ? P.ell_slot : nullptr, P.geom,
+                     ell ? P.ell_src : nullptr, ell ? P.ell_meta : nullptr, P.geom,
                      (const int32_t *)M.diag, P.div ? P.dsrc : nullptr);
   MPK_HIP(hipGetLastError());
   int32_t tot = 0;
@@ -191,8 +191,11 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   HostCsr ht;
   const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
   {
-    // the schedules of the two (four) sweeps are independent: build them on
-    // separate host threads
+    // the schedules of the two (four) sweeps are independent: the backward
+    // (and adjoint) ones are built on other host threads.  The forward
+    // sweep's global levels give the factorisation order, so the level-by-
+    // level factorisation is launched as soon as they exist and runs on the
+    // device while the blocked schedules are built on the host.
     std::thread t1([&] { build_plan(h, nullptr, 1, br, hp[1]); });
     std::thread t2;
     if (adj) {
@@ -207,14 +210,27 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
         t4.join();
       });
     }
-    build_plan(h, nullptr, 0, br, hp[0]);
+    build_plan_levels(h, nullptr, 0, br, hp[0]);
+    M->h_fac_levptr = hp[0].glob_levptr;
+    int32_t init[3] = {0, INT_MAX, INT_MAX};
+    if (hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess)
+      st = MPK_EDEVICE;
+    if (!st) {
+      hipLaunchKernelGGL(promote_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, KF,
+                         A->val, M->f);
+      st = hipGetLastError() != hipSuccess ? MPK_EDEVICE : MPK_OK;
+    }
+    if (!st)
+      st = (C == 1 ? (KF == 1 ? ilu0_levels<1, 1>(*M, s) : ilu0_levels<1, 2>(*M, s))
+                   : (KF == 1 ? ilu0_levels<2, 1>(*M, s) : ilu0_levels<2, 2>(*M, s)));
+    build_plan_blocks(h, nullptr, 0, br, hp[0]);
     t1.join();
     if (adj) t2.join();
+    if (st) return st;
   }
-  MPK_PHASE("build plans (host)");
-  M->h_fac_levptr = hp[0].glob_levptr;
-  MPK_HIP(hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
-                         hipMemcpyHostToDevice, s));
+  MPK_PHASE("levels, factor launch, plans (host)");
   Plan *P[4] = {&M->L, &M->U, &M->UH, &M->LH};
   for (int k = 0; k < (adj ? 4 : 2); ++k) P[k]->n = A->n;
   if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
@@ -240,16 +256,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     for (int k = 0; k < 2; ++k)
       if ((st = device_plan_arrays(*P[k], *M, k, s))) return st;
   }
-  MPK_PHASE("upload plans");
-  int32_t init[3] = {0, INT_MAX, INT_MAX};
-  MPK_HIP(hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(promote_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, KF, A->val,
-                     M->f);
-  MPK_HIP(hipGetLastError());
-  st = (C == 1 ? (KF == 1 ? ilu0_levels<1, 1>(*M, s) : ilu0_levels<1, 2>(*M, s))
-               : (KF == 1 ? ilu0_levels<2, 1>(*M, s) : ilu0_levels<2, 2>(*M, s)));
-  if (st) return st;
-  MPK_PHASE("factor levels");
+  MPK_PHASE("upload plans (after the factorisation)");
   int32_t badpiv = INT_MAX;
   MPK_HIP(hipMemcpyAsync(&badpiv, M->words + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MPK_HIP(hipStreamSynchronize(s));
@@ -282,14 +289,14 @@ static void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
     }();
     if (one_wave && P.max_piece <= WAVE)
       hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, WAVE>), dim3(grid ? grid : 1),
-                         dim3(WAVE), lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r,
-                         P.blk_lev, P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot,
+                         dim3(WAVE), lds, s, P.n, P.ptr, P.col, P.val, P.dval, P.blk_r,
+                         P.blk_lev, P.loc_pos, P.nblk, P.ell_col, P.ell_meta,
                          P.ell_val, P.blk_rows, rhs, out, P.sync,
                          abort_flag, done);
     else
       hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, BLOCK>), dim3(grid ? grid : 1),
-                         dim3(BLOCK), lds, s, P.n, P.order, P.ptr, P.col, P.val, P.dval, P.blk_r,
-                         P.blk_lev, P.loc_pos, P.nblk, P.ell_nd, P.ell_col, P.ell_slot,
+                         dim3(BLOCK), lds, s, P.n, P.ptr, P.col, P.val, P.dval, P.blk_r,
+                         P.blk_lev, P.loc_pos, P.nblk, P.ell_col, P.ell_meta,
                          P.ell_val, P.blk_rows, rhs, out, P.sync,
                          abort_flag, done);
     return;

@@ -277,6 +277,30 @@ def test_solve_parity(mpk, orc, name, method, K, kf, tol):
     assert info["relres_true"] <= tol
 
 
+@pytest.mark.parametrize("method,K,kf", [("bicgstab", 2, 1), ("bicg", 2, 1), ("gpbicg", 3, 2)])
+def test_solve_parity_deep_blocks(mpk, orc, monkeypatch, method, K, kf):
+    """Whole solves on blocked sweeps with blocks several planes deep (small
+    blocks forced on a 20^3 grid, so sweeps cross many of them): the same
+    checks as the other solve cases against the oracle."""
+    monkeypatch.setenv("MPK_TRSV_BLOCK_ROWS", "256")
+    p = W.config2(20)
+    tol = 1e-25 if K == 2 else 1e-35
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K))
+    ref = orc.krylov(method, p.row_ptr, p.col_idx, p.val, b, kf=kf, tol_rel=tol, max_iter=3000,
+                     hist_len=3000)
+    assert ref["status"] == 0, ref["status"]
+    A = mpk.Csr.from_problem(p)
+    x, info = mpk.krylov_solve(method, A, dev(b), fprec=kf, tol_rel=tol, max_iter=3000,
+                               hist_len=3000)
+    assert info["status"] == "ok", info
+    rel = true_relres_qd(orc, p, host(x), b) if K <= 2 else info["relres_true"]
+    assert rel <= tol * 1.01, (rel, tol)
+    assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
+    h, ho = host(info["hist"]), ref["hist"]
+    m = min(20, len(h), len(ho))
+    assert np.allclose(h[:m], ho[:m], rtol=1e-12, atol=0)
+
+
 def test_solve_breakdown_and_max_iter(mpk, orc):
     A = mpk.Csr([0, 2, 4], [0, 1, 0, 1], [0.0, 1.0, 1.0, 0.0])
     b = np.zeros((2, 1, 2))

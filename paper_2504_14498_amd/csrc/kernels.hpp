@@ -46,18 +46,33 @@ __device__ __forceinline__ void block_reduce(el<C, K> (&d)[ND], double *out) {
 
 // Sum of per-block partials [nblk][ND][C*K] by one workgroup: thread t
 // accumulates blocks t, t+256, ... in order, then block_reduce.  The
-// totals are valid in thread 0 only.
+// totals are valid in thread 0 only.  The loads of U consecutive blocks
+// of a thread are issued before their sums, so the memory round trips
+// overlap; the summation order stays the same.
 template <int C, int K, int ND>
 __device__ __forceinline__ void reduce_partials(const double *partials, int nblk,
                                                 el<C, K> (&tot)[ND]) {
+  constexpr int W = ND * C * K;
+  constexpr int U = W <= 4 ? 8 : (W <= 16 ? 4 : 2);
 #pragma unroll
   for (int q = 0; q < ND; ++q) tot[q] = el_zero<C, K>();
-  for (int b = threadIdx.x; b < nblk; b += BLOCK)
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += U * BLOCK) {
+    el<C, K> v[U][ND];
 #pragma unroll
-    for (int q = 0; q < ND; ++q) {
-      el<C, K> v = el_load<C, K>(partials + (size_t(b) * ND + q) * C * K);
-      tot[q] = (b == int(threadIdx.x)) ? v : el_add<C, K>(tot[q], v);
+    for (int u = 0; u < U; ++u) {
+      const int b = min(b0 + u * BLOCK, nblk - 1);  // in range; extra copies unused
+#pragma unroll
+      for (int q = 0; q < ND; ++q) v[u][q] = el_load<C, K>(partials + (size_t(b) * ND + q) * C * K);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * BLOCK;
+      if (b < nblk)
+#pragma unroll
+        for (int q = 0; q < ND; ++q)
+          tot[q] = (b == int(threadIdx.x)) ? v[u][q] : el_add<C, K>(tot[q], v[u][q]);
+    }
+  }
   block_reduce<C, K, ND>(tot, nullptr);
 }
 

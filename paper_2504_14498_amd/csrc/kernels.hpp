@@ -729,18 +729,18 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
       const int32_t j = r.cj[d];
       yl[d] = el_load<C, K>(lds + size_t(d < pe && j < 0 ? -j - 1 : spare) * E);
     }
-    // (bitwise operators: no short-circuit branches)
+    // Any prefetched word still holding the sentinel.  Slots that are not
+    // external were loaded from an out-of-range offset and hold zero, so
+    // they need no mask here; wait_ext re-checks with the masks.  (Bitwise
+    // operators: no short-circuit branches.)
     bool bad = false;
 #pragma unroll
-    for (int d = 0; d < MAXD; ++d) {
-      bool hit = false;
+    for (int d = 0; d < MAXD; ++d)
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int k = 0; k < K; ++k)
-          hit = hit | (__builtin_bit_cast(uint64_t, r.ye[d].c[c].v[k]) == SENTINEL);
-      bad = bad | ((d < pe) & (r.cj[d] >= 0) & hit);
-    }
+          bad = bad | (__builtin_bit_cast(uint64_t, r.ye[d].c[c].v[k]) == SENTINEL);
     if (bad) wait_ext<C, K, KF, MAXD>(r, pe, B, abort_flag);
 #pragma unroll
     for (int d = 0; d < MAXD; ++d)

@@ -54,6 +54,7 @@ def lib():
         L.or_ilu0_apply.argtypes = [i64, _I32, _I32, _D, c_int, c_int, c_int, _D, _D]
         L.or_ilu0_apply_h.argtypes = [i64, _I32, _I32, _D, c_int, c_int, c_int, _D, _D]
         L.or_dot.argtypes = [i64, c_int, c_int, _D, _D, _D]
+        L.or_residual.argtypes = [i64, _I32, _I32, _D, c_int, _D, c_int, _D, c_int, _D]
         L.or_krylov.argtypes = [c_int, i64, _I32, _I32, _D, c_int, c_int, c_int, _D, _D,
                                 dbl, dbl, i64, _I64, _D, _D, _I64, _D, i64]
         L.or_krylov.restype = c_int
@@ -215,6 +216,33 @@ def dot(a, b):
     out = np.zeros((C, K))
     lib().or_dot(n, C, K, _d(a), _d(b), _d(out))
     return out
+
+
+def residual(rp, ci, val, b, x):
+    """r = b - A x computed without rounding (a long accumulator), each
+    component then rounded to binary64: float64 (n, C).  b: (n, C, kb),
+    x: (n, C, kx), any limb counts."""
+    b, x = _f64(b), _f64(x)
+    n, C, kb = b.shape
+    kx = x.shape[2]
+    if x.shape[:2] != (n, C):
+        raise ValueError("b and x must have the same (n, C)")
+    rp, ci, val = _csr(rp, ci, val, C)
+    r = np.zeros((n, C))
+    lib().or_residual(n, _i32(rp), _i32(ci), _d(val), C, _d(b), kb, _d(x), kx, _d(r))
+    return r
+
+
+def true_relres(rp, ci, val, b, x):
+    """||b - A x||_2 / ||b||_2 with the residual computed exactly (see
+    residual); the norms are formed in binary64 from the rounded
+    components."""
+    r = residual(rp, ci, val, b, x)
+    zero = np.zeros((b.shape[0], b.shape[1], 1))
+    bb = residual(rp, ci, val, b, zero)
+    nb = float(np.sqrt(np.sum(bb * bb)))
+    nr = float(np.sqrt(np.sum(r * r)))
+    return nr / nb if nb > 0 else nr
 
 
 def krylov(method, rp, ci, val, b, kf, tol_rel, tol_abs=0.0, max_iter=1000, x0=None,

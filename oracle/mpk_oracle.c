@@ -755,6 +755,176 @@ void or_dot(int64_t n, int C, int K, const double *a, const double *b, double *o
 }
 
 /* ------------------------------------------------------------------ */
+/* Exact residual (the check on a solution that Algorithm 3's stopping  */
+/* rule asks for, computed without rounding)                            */
+/* ------------------------------------------------------------------ */
+
+/* A long fixed-point accumulator in the manner of Kulisch: digit k holds
+ * a signed multiple of 2^(32 k + ACC_LOW).  Every binary64 product of two
+ * binary64 numbers, and every binary64 number, is an integer of at most
+ * 106 bits times a power of two no smaller than 2^-2252 and no larger than
+ * 2^1942, so it enters the accumulator exactly; carries are resolved only
+ * when the total is read.  Nothing is rounded until the final conversion
+ * to binary64. */
+#define ACC_LOW (-2272)
+#define ACC_WORDS 140
+
+typedef struct {
+    int64_t d[ACC_WORDS];
+    int lo, hi; /* range of digits touched since the last clear */
+} acc_t;
+
+static void acc_clear(acc_t *a)
+{
+    int k;
+    for (k = 0; k < ACC_WORDS; ++k)
+        a->d[k] = 0;
+    a->lo = ACC_WORDS;
+    a->hi = -1;
+}
+
+/* a += sign * m * 2^e, m < 2^106 */
+static void acc_add_int(acc_t *a, unsigned __int128 m, int e, int neg)
+{
+    int off = e - ACC_LOW, w = off >> 5, s = off & 31, k;
+    for (k = 0; k < 4; ++k) {
+        uint64_t c = (uint64_t)(m >> (32 * k)) & 0xFFFFFFFFull;
+        uint64_t sh = c << s; /* < 2^63 */
+        int64_t lo = (int64_t)(sh & 0xFFFFFFFFull), hi = (int64_t)(sh >> 32);
+        if (neg) {
+            lo = -lo;
+            hi = -hi;
+        }
+        a->d[w + k] += lo;
+        a->d[w + k + 1] += hi;
+    }
+    if (w < a->lo)
+        a->lo = w;
+    if (w + 4 > a->hi)
+        a->hi = w + 4;
+}
+
+/* binary64 x = (-1)^neg * m * 2^e with m an integer below 2^53 */
+static void split_double(double x, uint64_t *m, int *e, int *neg)
+{
+    int ex;
+    double f = frexp(fabs(x), &ex);
+    *neg = x < 0;
+    *m = (uint64_t)ldexp(f, 53);
+    *e = ex - 53;
+}
+
+static void acc_add(acc_t *a, double x)
+{
+    uint64_t m;
+    int e, neg;
+    if (x == 0.0)
+        return;
+    split_double(x, &m, &e, &neg);
+    acc_add_int(a, (unsigned __int128)m, e, neg);
+}
+
+/* a += sign * x * y, exactly */
+static void acc_add_prod(acc_t *a, double x, double y, int sign)
+{
+    uint64_t mx, my;
+    int ex, ey, nx, ny;
+    if (x == 0.0 || y == 0.0)
+        return;
+    split_double(x, &mx, &ex, &nx);
+    split_double(y, &my, &ey, &ny);
+    acc_add_int(a, (unsigned __int128)mx * my, ex + ey, (nx ^ ny) ^ (sign < 0));
+}
+
+/* The accumulated total rounded to binary64 (to within two units in the
+ * last place; not necessarily the nearest). */
+static double acc_value(acc_t *a)
+{
+    int k, top, neg = 0;
+    double v;
+    if (a->hi < 0)
+        return 0.0;
+    for (k = a->lo; k < ACC_WORDS - 1 && k <= a->hi; ++k) {
+        int64_t carry = a->d[k] >> 32; /* floor division by 2^32 */
+        a->d[k] -= carry * ((int64_t)1 << 32);
+        a->d[k + 1] += carry;
+        if (k == a->hi && carry != 0)
+            a->hi = k + 1;
+    }
+    top = a->hi;
+    while (top >= a->lo && a->d[top] == 0)
+        --top;
+    if (top < a->lo)
+        return 0.0;
+    if (a->d[top] < 0) {
+        /* negative total: negate the digits and resolve the borrows again */
+        neg = 1;
+        for (k = a->lo; k <= top; ++k)
+            a->d[k] = -a->d[k];
+        for (k = a->lo; k < top; ++k) {
+            int64_t carry = a->d[k] >> 32;
+            a->d[k] -= carry * ((int64_t)1 << 32);
+            a->d[k + 1] += carry;
+        }
+        while (top >= a->lo && a->d[top] == 0)
+            --top;
+    }
+    v = 0.0;
+    for (k = top; k >= a->lo && k >= top - 2; --k)
+        v += ldexp((double)a->d[k], 32 * k + ACC_LOW);
+    return neg ? -v : v;
+}
+
+/* r = b - A x without rounding, then each component rounded to binary64:
+ * r[i*C + c] (C = 2: real then imaginary part).  b has kb limbs and x has
+ * kx limbs per component, in the vector layout above; A is binary64 (the
+ * complex product uses its four real products).  Used to check a
+ * solution's true residual ||b - A x|| independently of the arithmetic
+ * the methods run in. */
+void or_residual(int64_t n, const int32_t *rp, const int32_t *ci, const double *val, int C,
+                 const double *b, int kb, const double *x, int kx, double *r)
+{
+    int64_t i, p;
+    acc_t *acc = (acc_t *)malloc(sizeof(acc_t));
+    acc_clear(acc);
+    for (i = 0; i < n; ++i) {
+        int c, k;
+        for (c = 0; c < C; ++c) {
+            for (k = 0; k < kb; ++k)
+                acc_add(acc, b[(i * C + c) * kb + k]);
+            for (p = rp[i]; p < rp[i + 1]; ++p) {
+                const double *xj = x + (int64_t)ci[p] * C * kx;
+                if (C == 1) {
+                    for (k = 0; k < kx; ++k)
+                        acc_add_prod(acc, val[p], xj[k], -1);
+                } else if (c == 0) {
+                    /* re(a x) = a_re x_re - a_im x_im */
+                    for (k = 0; k < kx; ++k) {
+                        acc_add_prod(acc, val[2 * p], xj[k], -1);
+                        acc_add_prod(acc, val[2 * p + 1], xj[kx + k], +1);
+                    }
+                } else {
+                    /* im(a x) = a_re x_im + a_im x_re */
+                    for (k = 0; k < kx; ++k) {
+                        acc_add_prod(acc, val[2 * p], xj[kx + k], -1);
+                        acc_add_prod(acc, val[2 * p + 1], xj[k], -1);
+                    }
+                }
+            }
+            r[i * C + c] = acc_value(acc);
+            {
+                int lo = acc->lo, hi = acc->hi;
+                for (k = lo; k <= hi + 1 && k < ACC_WORDS; ++k)
+                    acc->d[k] = 0;
+                acc->lo = ACC_WORDS;
+                acc->hi = -1;
+            }
+        }
+    }
+    free(acc);
+}
+
+/* ------------------------------------------------------------------ */
 /* Krylov methods                                                       */
 /* ------------------------------------------------------------------ */
 

@@ -258,6 +258,16 @@ int mpk_gnn_forward(const mpk_csr *A, const void *graph, const float *params, fl
 int mpk_gnn_backward(const mpk_csr *A, const void *graph, const float *params,
                      const float *ddelta, float *dparams, void *ws, size_t ws_bytes,
                      void *stream);
+/* Copies an activation the last mpk_gnn_forward left in ws to out (device,
+ * bfloat16 bit patterns, rows x 32, row-major), so that a check of the
+ * backward pass can start from exactly the values it uses.  which: 0 =
+ * node states h (layer 0..3: the encoder output, then after each message-
+ * passing layer; n rows), 1 = edge states e (layer 0..3; nnz rows), 2 =
+ * messages m (layer 0..2; nnz rows), 3 = row means g (layer 0..2; n
+ * rows), 4 = relu of the node update, R(relu(Wu [h; g] + bu)) (layer
+ * 0..2; n rows).  Asynchronous; MPK_EINVAL for another which or layer. */
+int mpk_gnn_saved(const mpk_csr *A, const void *ws, size_t ws_bytes, int which, int layer,
+                  uint16_t *out, void *stream);
 /* Training loss of a correction delta on probe vectors w_p (nprobe rows of
  * n doubles, e.g. normalised residuals of the plain method), in binary64:
  *   loss = mean_p ||A w_p - L~ U~ w_p||^2 / ||A w_p||^2

@@ -176,6 +176,26 @@ def forward(theta, rp, ci, x, y, bf16_acts=True):
     return delta, saved
 
 
+def saved_from(theta, rp, ci, x, y, h, e, m, g, r):
+    """The saved state backward() needs, built from given stored
+    activations instead of a forward pass: h, e (LAYERS + 1 arrays each:
+    encoder outputs, then after each layer), m, g and r (LAYERS arrays: the
+    messages, the row means and R(relu(u)) of each layer).  backward() uses
+    z, u, pre_n and pre_e only through their signs, and those are the signs
+    of m, r, h[0] and e[0] (bfloat16 keeps float32's exponent range, so R()
+    maps no positive value to zero)."""
+    P = unpack(theta)
+    G = Graph(rp, ci)
+    saved = {"G": G, "x": x, "y": y, "pre_n": h[0], "pre_e": e[0], "layers": []}
+    for l in range(LAYERS):
+        saved["layers"].append({"h": h[l], "e": e[l], "z": m[l], "m": m[l], "g": g[l],
+                                "u": r[l], "Wm": bf16(P["Wm%d" % l]),
+                                "Wu": bf16(P["Wu%d" % l])})
+    saved["h"], saved["e"] = h[LAYERS], e[LAYERS]
+    saved["Xd"] = np.concatenate([h[LAYERS][G.row], h[LAYERS][G.col], e[LAYERS]], axis=1)
+    return saved
+
+
 def backward(theta, saved, gdelta):
     """Gradient of sum_q gdelta_q delta_q with respect to theta (float64)."""
     P = unpack(theta)

@@ -955,6 +955,30 @@ int mpk_gnn_backward(const mpk_csr *A, const void *graph, const float *params,
   return MPK_OK;
 }
 
+int mpk_gnn_saved(const mpk_csr *A, const void *ws, size_t ws_bytes, int which, int layer,
+                  uint16_t *out, void *stream) {
+  if (validate_csr_args(A) || !ws || !out) return MPK_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < mpk_gnn_workspace_bytes(A))
+    return MPK_EWORKSPACE;
+  const int nlayer = (which <= 1) ? NLAYER + 1 : NLAYER;
+  if (which < 0 || which > 4 || layer < 0 || layer >= nlayer) return MPK_EINVAL;
+  GWork W;
+  Bump b(const_cast<void *>(ws));
+  work_layout(A->n, A->nnz, b, &W);
+  const uint16_t *src = nullptr;
+  int64_t rows = A->n;
+  switch (which) {
+    case 0: src = W.h[layer]; break;
+    case 1: src = W.e[layer]; rows = A->nnz; break;
+    case 2: src = W.m[layer]; rows = A->nnz; break;
+    case 3: src = W.g[layer]; break;
+    default: src = W.r[layer]; break;
+  }
+  MPK_HIP(hipMemcpyAsync(out, src, sizeof(uint16_t) * size_t(rows) * HID,
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return MPK_OK;
+}
+
 size_t mpk_gnn_loss_workspace_bytes(const mpk_csr *A, int32_t nprobe) {
   if (!A || A->n <= 0 || A->nnz < 0 || nprobe <= 0) return 0;
   Bump b(nullptr);

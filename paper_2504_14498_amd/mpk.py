@@ -78,6 +78,7 @@ SIGNATURES = [
     ("mpk_gnn_workspace_bytes", _S, [_CSRP]),
     ("mpk_gnn_forward", _I, [_CSRP, _P, _P, _P, _P, _S, _P]),
     ("mpk_gnn_backward", _I, [_CSRP, _P, _P, _P, _P, _P, _S, _P]),
+    ("mpk_gnn_saved", _I, [_CSRP, _P, _S, _I, _I, _P, _P]),
     ("mpk_gnn_loss_workspace_bytes", _S, [_CSRP, ctypes.c_int32]),
     ("mpk_gnn_factor_loss", _I, [_CSRP, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _S, _P]),
     ("mpk_gnn_adam", _I, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -424,6 +425,21 @@ def gnn_backward(G, params, ddelta, workspace, dparams=None, stream=None):
                                    _ptr(ddelta), _ptr(dparams), ctypes.c_void_p(wp), wn,
                                    _stream(stream)), "gnn_backward")
     return dparams
+
+
+GNN_SAVED = {"h": 0, "e": 1, "m": 2, "g": 3, "r": 4}
+
+
+def gnn_saved(G, workspace, which, layer, stream=None):
+    """A stored activation of the last forward in workspace, as int16
+    (bfloat16 bit patterns) of shape (rows, 32)."""
+    A = G.A
+    rows = A.nnz if which in ("e", "m") else A.n
+    out = torch.empty((rows, 32), dtype=torch.int16, device=A.device)
+    _, wp, wn = workspace
+    _check(_lib().mpk_gnn_saved(ctypes.byref(A.c), ctypes.c_void_p(wp), wn, GNN_SAVED[which],
+                                int(layer), _ptr(out), _stream(stream)), "gnn_saved")
+    return out
 
 
 def gnn_factor_loss(G, M, delta, probes, grad=True, workspace=None, stream=None):

@@ -1,6 +1,7 @@
 """GPU parity of the batched persistent solver (one launch, many uneven
 systems): every system against the oracle (true residual and iteration
-count), bitwise identity across schedules, and per-system error reports."""
+count; the true residual of the GPU's x recomputed exactly by the oracle),
+bitwise identity across schedules, and per-system error reports."""
 import numpy as np
 import pytest
 
@@ -17,6 +18,12 @@ def mpk():
     from paper_2504_14498_amd import mpk as m
     m.library()
     return m
+
+
+# The device stops when its own K-limb true residual passes the test; the
+# exact residual differs from that by a rounding of the norms (binary64 on
+# both sides), far below this margin.
+RES_MARGIN = 1 + 1e-8
 
 
 def dev(a):
@@ -50,16 +57,9 @@ def test_batched_every_system_converges_like_oracle(mpk, orc, solved):
                          max_iter=2000)
         assert ref["status"] == 0
         assert info["status"] == "ok", (p.name, info)
-        # true residual of the GPU's x, recomputed by the oracle in QD
-        xg = x.cpu().numpy()
-        x4 = np.zeros((p.n, 1, 4))
-        x4[:, :, :2] = xg
-        b4 = np.zeros((p.n, 1, 4))
-        b4[:, :, :2] = b
-        ax = orc.spmv(p.row_ptr, p.col_idx, p.val, x4)
-        r = np.array([[orc.add(b4[i, 0], -ax[i, 0])] for i in range(p.n)])
-        rel = np.sqrt(orc.dot(r, r)[0].sum() / orc.dot(b4, b4)[0].sum())
-        assert rel <= 1.01e-25, (p.name, rel)
+        # true residual of the GPU's x, recomputed exactly by the oracle
+        rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, x.cpu().numpy())
+        assert rel <= 1e-25 * RES_MARGIN, (p.name, rel)
         assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"]), \
             (p.name, info["iters"], ref["iters"])
 
@@ -96,11 +96,13 @@ def test_batched_precisions(mpk, orc, fprec, K):
     xs, infos, st, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=fprec,
                                                 tol_rel=tol, max_iter=3000)
     assert st == "ok", infos
-    for p, b, info in zip(probs, bs, infos):
+    for p, b, x, info in zip(probs, bs, xs, infos):
         ref = orc.krylov("bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=fprec, tol_rel=tol,
                          max_iter=3000)
         assert ref["status"] == 0
-        assert info["relres_true"] <= tol
+        assert info["status"] == "ok" and info["relres_true"] <= tol
+        rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, x.cpu().numpy())
+        assert rel <= tol * RES_MARGIN, (p.name, K, rel)
         assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
 
 

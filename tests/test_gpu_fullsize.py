@@ -1,9 +1,10 @@
 """GPU parity at the full sizes of the measured workloads, in the launch
 configuration the benchmark times: SpMV and ILU(0) apply of the 128^3
 convection-diffusion system against the oracle element by element, the
-headline solve checked through properties that hold at any size (sampled
-residual rows in quad-double, error against x_true), and the learned
-correction's network and loss on the 512^2 lognormal system."""
+headline solve against the oracle's own full-size solve (pass count,
+residual history) with the exact residual of the GPU's x over every row,
+the complex Helmholtz solve at 1024^2, the learned correction's network
+and loss on the 512^2 lognormal system, and the 512-system batch."""
 import numpy as np
 import pytest
 
@@ -60,52 +61,84 @@ def test_ilu0_apply_full_size_bitwise(mpk, orc, big):
     assert np.array_equal(z, ref)
 
 
-def sub_rows(p, rows):
-    """CSR of the chosen rows of A (original column indices)."""
-    rp = [0]
-    ci, val = [], []
-    for i in rows:
-        a, b = p.row_ptr[i], p.row_ptr[i + 1]
-        ci.extend(p.col_idx[a:b])
-        val.extend(p.val[a:b])
-        rp.append(len(ci))
-    return np.array(rp, dtype=np.int32), np.array(ci, dtype=np.int32), np.array(val)
+# The device stops when its own K-limb true residual passes the test; the
+# exact residual differs from that by a rounding of the norms (binary64 on
+# both sides), far below this margin.
+RES_MARGIN = 1 + 1e-8
 
 
 def test_headline_solve_full_size(mpk, orc, big):
-    """BiCGSTAB-DD with a binary64 factor to 1e-25 on the 128^3 system: the
-    device's true residual claim is re-derived from sampled rows in QD by
-    the oracle, and x is compared with x_true."""
+    """BiCGSTAB-DD with a binary64 factor to 1e-25 on the 128^3 system,
+    b = A x_true formed by the oracle.  The GPU's x is checked over all
+    2,097,152 rows with the oracle's exact residual, and the oracle's own
+    full-size solve (run meanwhile on a host thread) gives the pass count
+    and the recursive-residual history the GPU must follow."""
+    import concurrent.futures as cf
     p = big
-    import torch
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2))
+    max_iter = p.meta["max_iter"]
+    with cf.ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(orc.krylov, "bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=1,
+                        tol_rel=1e-25, max_iter=max_iter, hist_len=max_iter)
+        A = mpk.Csr.from_problem(p)
+        x, info = mpk.krylov_solve("bicgstab", A, dev(b), fprec=1, tol_rel=1e-25,
+                                   max_iter=max_iter, hist_len=max_iter)
+        assert info["status"] == "ok" and info["relres_true"] < 1e-25, info
+        xh = host(x)
+        rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, xh)
+        assert rel <= 1e-25 * RES_MARGIN, rel
+        err = np.max(np.abs(xh[:, 0, 0] + xh[:, 0, 1] - p.x_true))
+        assert err < 1e-18, err
+        ref = fut.result()
+    assert ref["status"] == 0, ref["status"]
+    assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"]), (info["iters"],
+                                                                             ref["iters"])
+    h, ho = host(info["hist"]), ref["hist"]
+    m = min(20, len(h), len(ho))
+    assert np.allclose(h[:m], ho[:m], rtol=1e-12, atol=0)
+    print("headline: GPU %d passes, oracle %d; exact relres %.3e" % (info["iters"], ref["iters"],
+                                                                    rel))
+
+
+def test_helmholtz_full_size_solve(mpk, orc):
+    """The complex shifted Helmholtz system at its full size (1024^2,
+    GPBiCG in complex DD with a complex binary64 factor, to 1e-25): the
+    GPU's x over all 1,048,576 rows with the oracle's exact residual."""
+    p = W.config3(1024)
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2))
     A = mpk.Csr.from_problem(p)
-    b = mpk.csr_spmv(A, dev(p.x_true_limbs(2)))
-    x, info = mpk.krylov_solve("bicgstab", A, b, fprec=1, tol_rel=1e-25,
+    x, info = mpk.krylov_solve("gpbicg", A, dev(b), fprec=1, tol_rel=1e-25,
                                max_iter=p.meta["max_iter"])
-    assert info["status"] == "ok" and info["relres_true"] < 1e-25
-    xh, bh = host(x), host(b)
-    # every residual component is bounded by the norm the device reports
-    nb = float(np.sqrt(np.sum(bh[:, 0, 0] ** 2)))
-    rows = np.random.default_rng(4).choice(p.n, 4000, replace=False)
-    rows.sort()
-    rp, ci, val = sub_rows(p, rows)
-    x4 = np.zeros((p.n, 1, 4))
-    x4[:, :, :2] = xh
-    # the sampled rows against the columns they touch, as one square CSR
-    # (extra rows empty, extra x entries zero)
-    uniq, inv = np.unique(ci, return_inverse=True)
-    N = max(len(rows), len(uniq))
-    rpN = np.concatenate([rp, np.full(N - len(rows), rp[-1], dtype=np.int32)])
-    xN = np.zeros((N, 1, 4))
-    xN[: len(uniq)] = x4[uniq]
-    ax = orc.spmv(rpN, inv.astype(np.int32), val, xN)[: len(rows)]
-    b4 = np.zeros((len(rows), 1, 4))
-    b4[:, :, :2] = bh[rows]
-    worst = max(abs(orc.add(b4[k, 0], -ax[k, 0])[0]) for k in range(len(rows)))
-    assert worst <= 1e-25 * nb, (worst, nb)
-    err = np.max(np.abs(xh[:, 0, 0] + xh[:, 0, 1] - p.x_true))
-    assert err < 1e-18, err
-    torch.cuda.synchronize()
+    assert info["status"] == "ok", info
+    rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, host(x))
+    assert rel <= 1e-25 * RES_MARGIN, rel
+    print("helmholtz 1024^2: %d passes, %.1f ms solve, exact relres %.3e" %
+          (info["iters"], info["solve_ms"], rel))
+
+
+def test_helmholtz_256_solve_matches_oracle(mpk, orc):
+    """The same complex Helmholtz family at 256^2, where the oracle's solve
+    takes about a minute: pass count within max(3, 5%) of the oracle's,
+    the first 20 recursive residuals to 1e-12, exact residual of x."""
+    p = W.config3(256)
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2))
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(orc.krylov, "gpbicg", p.row_ptr, p.col_idx, p.val, b, kf=1,
+                        tol_rel=1e-25, max_iter=10000, hist_len=10000)
+        A = mpk.Csr.from_problem(p)
+        x, info = mpk.krylov_solve("gpbicg", A, dev(b), fprec=1, tol_rel=1e-25, max_iter=10000,
+                                   hist_len=10000)
+        assert info["status"] == "ok", info
+        rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, host(x))
+        assert rel <= 1e-25 * RES_MARGIN, rel
+        ref = fut.result()
+    assert ref["status"] == 0
+    assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"]), (info["iters"],
+                                                                             ref["iters"])
+    h, ho = host(info["hist"]), ref["hist"]
+    m = min(20, len(h), len(ho))
+    assert np.allclose(h[:m], ho[:m], rtol=1e-12, atol=0)
 
 
 def test_learned_network_and_loss_full_size(mpk, orc):
@@ -153,31 +186,34 @@ def test_helmholtz_full_size_spmv_and_apply_bitwise(mpk, orc):
 
 
 def test_batched_full_workload_sampled(mpk, orc):
-    """The whole 512-system batch in one launch; every system's device
-    report must show convergence to 1e-25, and two sampled systems (the
-    largest and the smallest) are re-solved by the oracle: pass counts
-    agree to one and the device's x has a true residual below the
-    tolerance, recomputed by the oracle in quad-double."""
+    """The whole 512-system batch in one launch, with b = A x_true formed
+    by the oracle.  Every system's device report must show convergence to
+    1e-25; the GPU's x of 34 sampled systems (every 16th, the largest and
+    the smallest) must pass the oracle's exact residual, and the largest
+    and the smallest are re-solved by the oracle: pass counts agree to
+    one."""
     import concurrent.futures as cf
     with cf.ThreadPoolExecutor(16) as ex:
         probs = list(ex.map(W.config4_system, range(512)))
+        bs = list(ex.map(lambda p: orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2)),
+                         probs))
     mats = [mpk.Csr.from_problem(p) for p in probs]
-    bs = [mpk.csr_spmv(A, dev(p.x_true_limbs(2))) for A, p in zip(mats, probs)]
-    xs, infos, st, _ = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25, max_iter=200)
+    xs, infos, st, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
+                                                tol_rel=1e-25, max_iter=200)
     assert st == "ok"
     assert all(i["status"] == "ok" and i["relres_true"] < 1e-25 for i in infos)
     sizes = [p.n for p in probs]
-    for q in (int(np.argmax(sizes)), int(np.argmin(sizes))):
-        p = probs[q]
-        b = host(bs[q])
-        ref = orc.krylov("bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=1, tol_rel=1e-25,
-                         max_iter=200)
+    big_q, small_q = int(np.argmax(sizes)), int(np.argmin(sizes))
+    sample = sorted(set(range(0, 512, 16)) | {big_q, small_q})
+    xh = {q: host(xs[q]) for q in sample}
+    with cf.ThreadPoolExecutor(16) as ex:
+        rels = list(ex.map(lambda q: orc.true_relres(probs[q].row_ptr, probs[q].col_idx,
+                                                     probs[q].val, bs[q], xh[q]), sample))
+        refs = list(ex.map(lambda q: orc.krylov("bicgstab", probs[q].row_ptr, probs[q].col_idx,
+                                                probs[q].val, bs[q], kf=1, tol_rel=1e-25,
+                                                max_iter=200), (big_q, small_q)))
+    for q, rel in zip(sample, rels):
+        assert rel <= 1e-25 * RES_MARGIN, (q, rel)
+    for q, ref in zip((big_q, small_q), refs):
         assert ref["status"] == 0
         assert abs(ref["iters"] - infos[q]["iters"]) <= 1, (q, ref["iters"], infos[q]["iters"])
-        x4 = np.zeros((p.n, 1, 4))
-        x4[:, :, :2] = host(xs[q])
-        ax = orc.spmv(p.row_ptr, p.col_idx, p.val, x4)
-        b4 = np.zeros((p.n, 1, 4))
-        b4[:, :, :2] = b
-        r = np.array([orc.add(b4[i, 0], -ax[i, 0])[0] for i in range(p.n)])
-        assert np.sqrt(np.sum(r * r)) < 1e-25 * np.sqrt(np.sum(b[:, 0, 0] ** 2))

@@ -143,6 +143,28 @@ def test_backward_vs_finite_differences():
         assert abs(fd - g @ v) <= 1e-6 * max(1.0, abs(fd))
 
 
+def test_backward_from_stored_activations_equals_forward_state():
+    """backward() started from the stored bfloat16 activations alone (the
+    state a device keeps) gives the same gradient as from the forward's
+    full state: its masks only need the signs of m, R(relu(u)), h0, e0."""
+    rp, ci, val = tiny_pattern(30, 8, density=0.2)
+    f = plain_factor(rp, ci, val)
+    x, y = gnn.features(rp, ci, val, f)
+    th = random_theta(9)
+    gd = np.random.default_rng(10).standard_normal(len(ci))
+    _, S = gnn.forward(th, rp, ci, x, y, bf16_acts=True)
+    L = S["layers"]
+    relu = lambda a: np.maximum(a, 0.0)
+    h = [l["h"] for l in L] + [S["h"]]
+    e = [l["e"] for l in L] + [S["e"]]
+    m = [l["m"] for l in L]
+    g = [l["g"] for l in L]
+    r = [gnn.bf16(relu(l["u"])) for l in L]
+    assert all(np.any(v == 0) and np.any(v > 0) for v in r + m)
+    saved = gnn.saved_from(th, rp, ci, x, y, h, e, m, g, r)
+    assert np.array_equal(gnn.backward(th, saved, gd), gnn.backward(th, S, gd))
+
+
 def tridiag(n, seed):
     rng = np.random.default_rng(seed)
     rp = [0]

@@ -435,7 +435,7 @@ static void el_conj(int C, int K, const double *x, double *z)
 
 /* x / d where d has kd limbs per component: real case is a plain division;
  * complex case is x * conj(d) / |d|^2, all in K limbs, without scaling. */
-static void el_div_k(int C, int K, const double *x, const double *d, int kd, double *z)
+static void el_div_k_direct(int C, int K, const double *x, const double *d, int kd, double *z)
 {
     if (C == 1) {
         mp_div_k(K, x, d, kd, z);
@@ -458,6 +458,29 @@ static void el_div_k(int C, int K, const double *x, const double *d, int kd, dou
         mp_div(K, nr, den, z);
         mp_div(K, ni, den, z + K);
     }
+}
+
+/* x / d.  Complex: x conj(d) / |d|^2, which squares the magnitude of d;
+ * when the leading limbs of d lie outside [2^-300, 2^300] (where |d|^2
+ * and its lower limbs would leave the binary64 range), d is first scaled
+ * by a power of two 2^-e, which is exact, and the quotient by 2^-e
+ * afterwards: x / d = (x / (d 2^-e)) 2^-e.  Inside that range the direct
+ * formula is used, so its results are unchanged; outside it they are the
+ * direct formula's as if the range were unbounded. */
+static void el_div_k(int C, int K, const double *x, const double *d, int kd, double *z)
+{
+    double m = C == 2 ? fmax(fabs(d[0]), fabs(d[kd])) : 0.0;
+    if (C == 2 && isfinite(m) && m != 0.0 && (m < 0x1p-300 || m > 0x1p300)) {
+        double ds[2 * KMAX];
+        int e = ilogb(m), i;
+        for (i = 0; i < 2 * kd; ++i)
+            ds[i] = ldexp(d[i], -e);
+        el_div_k_direct(C, K, x, ds, kd, z);
+        for (i = 0; i < 2 * K; ++i)
+            z[i] = ldexp(z[i], -e);
+        return;
+    }
+    el_div_k_direct(C, K, x, d, kd, z);
 }
 
 static void el_div(int C, int K, const double *x, const double *d, double *z)

@@ -150,3 +150,30 @@ def test_complex_mul_div(orc, K):
         qmag = (abs(xr) + abs(xi)) * (abs(sr) + abs(si)) / d2
         assert abs(fr(q[0]) - qr) <= 4 * tol * qmag
         assert abs(fr(q[1]) - qi) <= 4 * tol * qmag
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_complex_div_outside_the_squared_range(orc, K):
+    """x / d for denominators far from 1 (|d| ~ 2^-700 .. 2^700, where |d|^2
+    leaves the binary64 range): the quotient equals the exact Gaussian
+    rational quotient within the same bound as near 1, and equals, bit for
+    bit, the quotient of the same operands brought near 1 by powers of two
+    (multiplying by a power of two is exact in binary64)."""
+    rng = np.random.default_rng(40 + K)
+    tol = 32 * U ** K
+    for shift_d, shift_x in [(-700, -700), (-600, -650), (-400, 0), (500, 480), (700, 700),
+                             (-350, -300), (310, 330), (200, 150), (-250, -260)]:
+        for _ in range(40):
+            s = np.stack([rand_mp(rng, orc, K), rand_mp(rng, orc, K)])
+            x = np.stack([rand_mp(rng, orc, K), rand_mp(rng, orc, K)])
+            q1 = orc.cdiv(x, s)
+            q = orc.cdiv(np.ldexp(x, shift_x), np.ldexp(s, shift_d))
+            assert np.all(np.isfinite(q))
+            assert np.array_equal(q, np.ldexp(q1, shift_x - shift_d))
+            sr, si = fr(np.ldexp(s[0], shift_d)), fr(np.ldexp(s[1], shift_d))
+            xr, xi = fr(np.ldexp(x[0], shift_x)), fr(np.ldexp(x[1], shift_x))
+            d2 = sr * sr + si * si
+            qr, qi = (xr * sr + xi * si) / d2, (xi * sr - xr * si) / d2
+            qmag = (abs(xr) + abs(xi)) * (abs(sr) + abs(si)) / d2
+            assert abs(fr(q[0]) - qr) <= tol * qmag
+            assert abs(fr(q[1]) - qi) <= tol * qmag

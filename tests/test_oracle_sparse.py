@@ -190,7 +190,7 @@ def test_ilu0_tridiagonal_is_exact_lu(orc):
     assert np.allclose(Uo, Um, rtol=1e-14, atol=1e-15)
 
 
-@pytest.mark.parametrize("kf,C", [(1, 1), (2, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("kf,C", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 1), (4, 1), (3, 2), (4, 2)])
 def test_ilu0_reproduces_a_on_pattern(orc, kf, C):
     """(L U)_ij = a_ij on the stored pattern, up to c u_kf (|L||U|)_ij,
     checked in exact rationals from the oracle's factor values."""
@@ -223,19 +223,29 @@ def test_ilu0_reproduces_a_on_pattern(orc, kf, C):
             assert abs(complex(s - A[i][j])) <= 16 * n * U ** kf * mag
 
 
-def test_ilu0_literal_exact_matches_oracle_dd(orc):
-    """Literal Algorithm 1 in exact rationals vs the oracle's double-word
-    factor: every factor value agrees to a few u^2 relative."""
-    p = W.random_pattern(20, 0.3, 77, dominance=1.1)
-    st, bad, f = orc.ilu0(p.row_ptr, p.col_idx, p.val, 1, 2)
-    A = X.csr_to_dense_q(p.row_ptr, p.col_idx, p.val, p.n, 1)
+@pytest.mark.parametrize("kf,C,bound", [(2, 1, 1e-28), (3, 1, 1e-44), (4, 1, 1e-59),
+                                         (3, 2, 1e-44), (4, 2, 1e-59)])
+def test_ilu0_literal_exact_matches_oracle(orc, kf, C, bound):
+    """Literal Algorithm 1 in exact rationals vs the oracle's double-,
+    triple- and quad-word factors (the paper's full-precision "ILU(0)"
+    variants): every factor value agrees to a few u^kf relative."""
+    p = W.random_pattern(20, 0.3, 77 + 10 * kf + C, complex_=(C == 2), dominance=1.1)
+    st, bad, f = orc.ilu0(p.row_ptr, p.col_idx, p.val, C, kf)
+    assert st == 0
+    A = X.csr_to_dense_q(p.row_ptr, p.col_idx, p.val, p.n, C)
     L, Uq = X.ilu0_literal(A)
+    worst = 0.0
     for i in range(p.n):
         for q in range(p.row_ptr[i], p.row_ptr[i + 1]):
             j = p.col_idx[q]
             ex = L[i][j] if j < i else Uq[i][j]
             got = X.limbs_to_q(f[q])
-            assert abs(complex(got - ex)) <= 1e-28 * max(1.0, abs(complex(ex)))
+            err = abs(complex(got - ex)) / max(1.0, abs(complex(ex)))
+            worst = max(worst, err)
+            assert err <= bound, (i, j, err)
+    # every limb counts: the error is far below the unit of a format one limb
+    # shorter
+    assert worst <= 2.0 ** (-53 * (kf - 1) - 20), worst
 
 
 def test_ilu0_errors(orc):
@@ -291,7 +301,8 @@ def test_apply_k1_vs_scipy_triangular(orc):
 
 
 @pytest.mark.parametrize("K,kf,C", [(2, 1, 1), (2, 2, 1), (4, 1, 1), (4, 2, 1), (3, 2, 2),
-                                    (2, 1, 2)])
+                                    (2, 1, 2), (3, 3, 1), (4, 3, 1), (4, 4, 1), (3, 3, 2),
+                                    (4, 4, 2)])
 def test_apply_exact_bound(orc, K, kf, C):
     """z = (L U)^{-1} r and (L U)^{-H} r against exact rational solves with
     the same (oracle) factor values."""

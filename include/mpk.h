@@ -109,7 +109,9 @@ int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x
 /* --------------------------------------------------------------- ILU(0)
  * ILU(0) factorisation (Algorithm 1) on the stored pattern of A, in factor
  * precision fp = MPK_D (binary64: the "_d_ILU(0)" factor of Section 4) or
- * MPK_DD (A promoted exactly to double-word).  "A_ij != 0" is read
+ * MPK_DD, MPK_TD, MPK_QD (A promoted exactly to fp limbs and factored in
+ * that arithmetic: the full-precision "ILU(0)" factors of Section 4,
+ * Tables 1 and 2).  "A_ij != 0" is read
  * structurally.  Rows are eliminated in IKJ order, level by level; each
  * entry receives the updates of Algorithm 1 in ascending k, so the factor
  * is identical to the KIJ loop's.  Zero pivots are reported
@@ -149,7 +151,7 @@ void mpk_ilu0_destroy(mpk_ilu0 *M);
  * BiCG exactly as Algorithm 3; CGS, BiCGSTAB and GPBiCG in right-
  * preconditioned form (unpreconditioned residual, two M-solves per pass).
  * vp: vector precision (MPK_D..MPK_QD).  fp: 0 = no preconditioner,
- * MPK_D or MPK_DD = ILU(0) factor precision.  Stopping rule of Algorithm 3,
+ * MPK_D..vp = ILU(0) factor precision.  Stopping rule of Algorithm 3,
  * ||r|| < tol_rel ||r_0|| + tol_abs, on the recursive residual; when it
  * passes, the true residual ||b - A x|| is evaluated in the working
  * precision and must pass the same test, otherwise the recursion goes on.

@@ -919,7 +919,7 @@ static int krylov_solve(int C, mpk_method m, mpk_prec vp, mpk_prec fp, double to
   }
   int st = validate_csr_args(A);
   if (!st && (m < MPK_BICG || m > MPK_GPBICG || vp < MPK_D || vp > MPK_QD || !b || !x ||
-              !(fp == 0 || fp == MPK_D || fp == MPK_DD) || int(fp) > int(vp) ||
+              !(fp == 0 || (fp >= MPK_D && fp <= MPK_QD)) || int(fp) > int(vp) ||
               !(tol_rel >= 0) || !(tol_abs >= 0) || max_iter < 0))
     st = MPK_EINVAL;
   if (!st && (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
@@ -943,7 +943,7 @@ extern "C" {
 size_t mpk_krylov_workspace_bytes(mpk_method m, mpk_prec vp, mpk_prec fp, const mpk_csr *A,
                                   int is_complex) {
   if (!A || A->n <= 0 || A->nnz < 0 || m < MPK_BICG || m > MPK_GPBICG || vp < MPK_D ||
-      vp > MPK_QD || !(fp == 0 || fp == MPK_D || fp == MPK_DD))
+      vp > MPK_QD || !(fp == 0 || (fp >= MPK_D && fp <= MPK_QD)))
     return 0;
   return krylov_bytes(m, is_complex ? 2 : 1, int(vp), int(fp), A->n, A->nnz);
 }

@@ -408,7 +408,11 @@ template <int C, int K> MPK_HD el<C, K> el_mul(const el<C, K> &s, const el<C, K>
 }
 
 // x / d with d of KD limbs per component: real case a plain division, the
-// complex case x conj(d) / |d|^2 in K limbs (no scaling).
+// complex case x conj(d) / |d|^2 in K limbs (no Smith scaling).  Squaring
+// |d| leaves the binary64 range when d's leading limbs are outside
+// [2^-300, 2^300]; then d is scaled by 2^-e first (exact) and the quotient
+// by 2^-e afterwards, x / d = (x / (d 2^-e)) 2^-e.  Inside that range e = 0
+// and the scalings are identities, so the direct formula's results stand.
 template <int C, int K, int KD>
 MPK_HD el<C, K> el_div_k(const el<C, K> &x, const double *d) {
   if constexpr (C == 1) {
@@ -416,18 +420,27 @@ MPK_HD el<C, K> el_div_k(const el<C, K> &x, const double *d) {
     z.c[0] = div_k<K, KD>(x.c[0], d);
     return z;
   } else {
+    const double mg = fmax(fabs(d[0]), fabs(d[KD]));
+    const int e = (isfinite(mg) && mg != 0.0 && (mg < 0x1p-300 || mg > 0x1p300)) ? ilogb(mg) : 0;
+    double ds[2 * KD];
+#pragma unroll
+    for (int i = 0; i < 2 * KD; ++i) ds[i] = ldexp(d[i], -e);
     mp<K> dr = mp_zero<K>(), di = mp_zero<K>();
 #pragma unroll
     for (int i = 0; i < KD; ++i) {
-      dr.v[i] = d[i];
-      di.v[i] = d[KD + i];
+      dr.v[i] = ds[i];
+      di.v[i] = ds[KD + i];
     }
-    mp<K> den = add<K>(mul_k<K, KD>(dr, d), mul_k<K, KD>(di, d + KD));
-    mp<K> nr = add<K>(mul_k<K, KD>(x.c[0], d), mul_k<K, KD>(x.c[1], d + KD));
-    mp<K> ni = sub<K>(mul_k<K, KD>(x.c[1], d), mul_k<K, KD>(x.c[0], d + KD));
+    mp<K> den = add<K>(mul_k<K, KD>(dr, ds), mul_k<K, KD>(di, ds + KD));
+    mp<K> nr = add<K>(mul_k<K, KD>(x.c[0], ds), mul_k<K, KD>(x.c[1], ds + KD));
+    mp<K> ni = sub<K>(mul_k<K, KD>(x.c[1], ds), mul_k<K, KD>(x.c[0], ds + KD));
     el<2, K> z;
     z.c[0] = div<K>(nr, den);
     z.c[1] = div<K>(ni, den);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int k = 0; k < K; ++k) z.c[c].v[k] = ldexp(z.c[c].v[k], -e);
     return z;
   }
 }

@@ -223,8 +223,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
       st = hipGetLastError() != hipSuccess ? MPK_EDEVICE : MPK_OK;
     }
     if (!st)
-      st = (C == 1 ? (KF == 1 ? ilu0_levels<1, 1>(*M, s) : ilu0_levels<1, 2>(*M, s))
-                   : (KF == 1 ? ilu0_levels<2, 1>(*M, s) : ilu0_levels<2, 2>(*M, s)));
+      st = dispatch_ck(C, KF, [&]<int CC, int KK>() { return ilu0_levels<CC, KK>(*M, s); });
     build_plan_blocks(h, nullptr, 0, br, hp[0]);
     t1.join();
     if (adj) t2.join();
@@ -341,6 +340,12 @@ int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z
   if (K > M.L.kmax) return MPK_EUNSUPPORTED;
   if (conj && !(M.flags & MPK_ILU0_ADJOINT)) return MPK_EUNSUPPORTED;
   return dispatch_ck(M.C, K, [&]<int C, int KK>() {
+    if constexpr (KK >= 4) {
+      if (M.KF == 4) return apply_ckf<C, KK, 4>(M, conj, r, z, abort_reset, abort_flag, done, s);
+    }
+    if constexpr (KK >= 3) {
+      if (M.KF == 3) return apply_ckf<C, KK, 3>(M, conj, r, z, abort_reset, abort_flag, done, s);
+    }
     if constexpr (KK >= 2) {
       if (M.KF == 2) return apply_ckf<C, KK, 2>(M, conj, r, z, abort_reset, abort_flag, done, s);
     }
@@ -443,7 +448,7 @@ int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x
 }
 
 size_t mpk_ilu0_workspace_bytes(const mpk_csr *A, mpk_prec fp, int is_complex, int flags) {
-  if (!A || A->n <= 0 || A->nnz < 0 || (fp != MPK_D && fp != MPK_DD)) return 0;
+  if (!A || A->n <= 0 || A->nnz < 0 || fp < MPK_D || fp > MPK_QD) return 0;
   Bump b(nullptr);
   return ilu0_layout(A->n, A->nnz, is_complex ? 2 : 1, int(fp), flags, b, nullptr);
 }
@@ -452,7 +457,7 @@ static int ilu0_factor(int C, mpk_prec fp, const mpk_csr *A, int flags, void *ws
                        mpk_ilu0 **M, mpk_info *info, void *stream) {
   int st = validate_csr_args(A);
   if (st) return st;
-  if ((fp != MPK_D && fp != MPK_DD) || !M || (flags & ~(MPK_ILU0_ADJOINT | (7 << 4))) ||
+  if (fp < MPK_D || fp > MPK_QD || !M || (flags & ~(MPK_ILU0_ADJOINT | (7 << 4))) ||
       ((flags >> 4) & 7) > 4 || (((flags >> 4) & 7) && ((flags >> 4) & 7) < int(fp)))
     return MPK_EINVAL;
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||

@@ -198,7 +198,8 @@ class Ilu0:
 
 
 def ilu0_factor(A, fprec=1, adjoint=False, vprec=None, stream=None):
-    """ILU(0) factorisation in binary64 (fprec=1) or double-double (2).
+    """ILU(0) factorisation in binary64 (fprec=1) or with 2, 3 or 4 limbs
+    (double-, triple-, quad-word).
     vprec: largest vector precision the factor will be applied with (sizes
     the on-chip blocks of the substitutions; default 4 = QD)."""
     flags = ILU0_ADJOINT if adjoint else 0

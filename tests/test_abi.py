@@ -82,9 +82,13 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                                  ctypes.c_void_p(8), ctypes.c_void_p(264), need, None, None) == -3
     assert lib.mpk_dkrylov_solve(2, 2, 1, 1e-25, 0.0, 10, ctypes.byref(A), ctypes.c_void_p(8),
                                  ctypes.c_void_p(8), ws, need - 1, None, None) == -3
-    # ILU(0): factor precision must be D or DD
+    # ILU(0): factor precision D..QD, not above the declared vector precision
     h = ctypes.c_void_p()
-    assert lib.mpk_dilu0_factor(3, ctypes.byref(A), 0, ws, 1 << 30, ctypes.byref(h), None,
+    assert lib.mpk_dilu0_factor(5, ctypes.byref(A), 0, ws, 1 << 30, ctypes.byref(h), None,
+                                None) == -1
+    assert lib.mpk_dilu0_factor(0, ctypes.byref(A), 0, ws, 1 << 30, ctypes.byref(h), None,
+                                None) == -1
+    assert lib.mpk_dilu0_factor(3, ctypes.byref(A), 2 << 4, ws, 1 << 30, ctypes.byref(h), None,
                                 None) == -1
     assert lib.mpk_dilu0_factor(1, ctypes.byref(A), 4, ws, 1 << 30, ctypes.byref(h), None,
                                 None) == -1
@@ -102,16 +106,20 @@ def test_workspace_queries_scale(lib):
     small, big = _csr(1000, 5000), _csr(100000, 500000)
     for m in range(4):
         for vp in (1, 2, 3, 4):
-            for fp in (0, 1, 2):
+            for fp in range(0, vp + 1):
                 a = lib.mpk_krylov_workspace_bytes(m, vp, fp, ctypes.byref(small), 0)
                 b = lib.mpk_krylov_workspace_bytes(m, vp, fp, ctypes.byref(big), 1)
                 assert 0 < a < b
                 # vectors alone: at least 8 vectors of n C K doubles
                 assert b >= 8 * 100000 * 2 * vp * 8
     assert lib.mpk_krylov_workspace_bytes(9, 2, 1, ctypes.byref(small), 0) == 0
-    assert lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 3, 0, 0) == 0
+    assert lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 5, 0, 0) == 0
+    # wider factors take more room
+    assert 0 < lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 2, 0, 0) < \
+        lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 4, 0, 0)
     assert lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 1, 0, 1) > \
         lib.mpk_ilu0_workspace_bytes(ctypes.byref(small), 1, 0, 0)
     assert lib.mpk_spmv_workspace_bytes(ctypes.byref(small), 0, 0) == 0
     assert lib.mpk_spmv_workspace_bytes(ctypes.byref(small), 1, 1) > 5000 * 16
     assert lib.mpk_dot_workspace_bytes(1000, 0, 2) >= 4 * 2 * 8
+

@@ -111,7 +111,8 @@ def test_spmv_transpose_bitwise(mpk, orc, name, K):
 
 @pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv2d", "conv2d_tail", "conv3d", "helm",
                                   "rdd"])
-@pytest.mark.parametrize("kf,K", [(1, 1), (1, 2), (2, 2), (1, 3), (2, 3), (1, 4), (2, 4)])
+@pytest.mark.parametrize("kf,K", [(1, 1), (1, 2), (2, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 3),
+                                  (3, 4), (4, 4)])
 def test_ilu0_apply_bitwise(mpk, orc, name, kf, K):
     p = case(name)
     A = mpk.Csr.from_problem(p)
@@ -248,6 +249,18 @@ SOLVE_CASES = [
     ("helm", "cgs", 4, 1, 1e-40),
     ("rdd", "bicgstab", 2, 1, 1e-25),
     ("rdd", "gpbicg", 3, 2, 1e-35),
+    # full-precision factors: triple- and quad-word ILU(0)
+    ("conv3d", "bicgstab", 3, 3, 1e-35),
+    ("conv3d", "bicg", 4, 4, 1e-50),
+    ("conv2d", "cgs", 4, 4, 1e-50),
+    ("helm", "gpbicg", 3, 3, 1e-35),
+    ("helm", "bicgstab", 4, 4, 1e-50),
+    ("rdd", "gpbicg", 4, 4, 1e-50),
+    ("rand_cplx", "bicg", 3, 3, 1e-35),
+    # complex GPBiCG in QD: its 2x2 system's denominator falls below
+    # 2^-300 near convergence (complex division with a scaled divisor)
+    ("helm", "gpbicg", 4, 4, 1e-50),
+    ("rand_cplx", "gpbicg", 4, 1, 1e-50),
 ]
 
 

@@ -300,6 +300,22 @@ size_t mpk_dot_workspace_bytes(int64_t n, int is_complex, mpk_prec p);
 int mpk_dot(mpk_prec p, int is_complex, int64_t n, const double *a, const double *b,
             double *out, void *ws, size_t ws_bytes, void *stream);
 
+/* The same inner product for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the partials go to a fixed 4 MiB
+ * device array of the library (one per GPU, held until the process ends,
+ * its address looked up on the first call on each device).  Same kernels
+ * and reduction tree as mpk_dot, so the result is bitwise identical.
+ * n may be at most mpk_dot_noalloc_max_elements(is_complex, p) (2^27 /
+ * (C K) rounded to whole workgroups of 256), otherwise MPK_EWORKSPACE
+ * before any device work.  Calls on one GPU share the array: calls that
+ * overlap in time on one GPU (different streams, or host threads) race and
+ * must be serialised by the caller.  Calls no hipMalloc/hipFree.
+ * Asynchronous on stream. */
+size_t mpk_dot_noalloc_max_elements(int is_complex, mpk_prec p);
+int mpk_dot_noalloc(mpk_prec p, int is_complex, int64_t n, const double *a, const double *b,
+                    double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

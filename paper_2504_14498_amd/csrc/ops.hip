@@ -4,6 +4,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <thread>
 
 #include "kernels.hpp"
@@ -369,6 +370,34 @@ __global__ __launch_bounds__(BLOCK) void dot_final(const double *partials, int n
   if (threadIdx.x == 0) el_store<C, K>(out, tot[0]);
 }
 
+// Fixed device scratch of the inner product that allocates nothing: the
+// per-workgroup partials of one mpk_dot_noalloc call.  Every GPU the library
+// runs on holds one copy until the process ends; calls on one GPU share it.
+constexpr size_t DOT_SCRATCH_DOUBLES = size_t(1) << 19;  // 4 MiB
+__device__ __align__(256) double dot_scratch[DOT_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex dot_scratch_mu;
+double *dot_scratch_ptr[MAX_DEVICES];
+
+// The device address of this GPU's dot_scratch, looked up once per device
+// (with that device current) on the first call.  The array's name is a
+// host-side stand-in, never passed to a kernel.
+int dot_scratch_address(double **out) {
+  int dev = 0;
+  MPK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return MPK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(dot_scratch_mu);
+  if (!dot_scratch_ptr[dev]) {
+    void *p = nullptr;
+    MPK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(dot_scratch)));
+    if (!p) return MPK_EDEVICE;
+    dot_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = dot_scratch_ptr[dev];
+  return MPK_OK;
+}
+
 }  // namespace mpk
 
 using namespace mpk;
@@ -520,6 +549,30 @@ int mpk_dot(mpk_prec p, int is_complex, int64_t n, const double *a, const double
     return MPK_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   double *part = static_cast<double *>(ws);
+  const int nb = int(nblocks(n));
+  return dispatch_ck(is_complex ? 2 : 1, int(p), [&]<int C, int K>() {
+    DotOp<C, K> op{a, b};
+    hipLaunchKernelGGL((row_kernel<C, K, 1, DotOp<C, K>>), dim3(xcd_grid(nb)), dim3(BLOCK), 0, s, n, op,
+                       (const int32_t *)nullptr, part);
+    hipLaunchKernelGGL((dot_final<C, K>), dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
+                       out);
+    return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
+  });
+}
+
+size_t mpk_dot_noalloc_max_elements(int is_complex, mpk_prec p) {
+  if (p < MPK_D || p > MPK_QD) return 0;
+  return DOT_SCRATCH_DOUBLES / size_t((is_complex ? 2 : 1) * int(p)) * BLOCK;
+}
+
+int mpk_dot_noalloc(mpk_prec p, int is_complex, int64_t n, const double *a, const double *b,
+                    double *out, void *stream) {
+  if (n <= 0 || p < MPK_D || p > MPK_QD || !a || !b || !out) return MPK_EINVAL;
+  if (size_t(n) > mpk_dot_noalloc_max_elements(is_complex, p)) return MPK_EWORKSPACE;
+  double *part = nullptr;
+  int st = dot_scratch_address(&part);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
   const int nb = int(nblocks(n));
   return dispatch_ck(is_complex ? 2 : 1, int(p), [&]<int C, int K>() {
     DotOp<C, K> op{a, b};

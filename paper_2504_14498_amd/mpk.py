@@ -86,6 +86,8 @@ SIGNATURES = [
     ("mpk_ilu0_correct", _I, [_P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("mpk_dot_workspace_bytes", _S, [_I64, _I, _I]),
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
+    ("mpk_dot_noalloc_max_elements", _S, [_I, _I]),
+    ("mpk_dot_noalloc", _I, [_I, _I, _I64, _P, _P, _P, _P]),
 ]
 
 
@@ -239,6 +241,19 @@ def dot(a, b, stream=None):
     ws, ws_ptr, ws_n = _workspace(nb, a.device)
     _check(_lib().mpk_dot(K, int(C == 2), n, _ptr(a), _ptr(b), _ptr(out), ctypes.c_void_p(ws_ptr),
                           ws_n, _stream(stream)), "dot")
+    return out
+
+
+def dot_noalloc_max_elements(C, K):
+    return _lib().mpk_dot_noalloc_max_elements(int(C == 2), K)
+
+
+def dot_noalloc(a, b, out, stream=None):
+    """<a, b> into the caller's out (C, K) with the library's fixed device
+    scratch: the call itself allocates nothing."""
+    n, C, K = a.shape
+    _check(_lib().mpk_dot_noalloc(K, int(C == 2), n, _ptr(a), _ptr(b), _ptr(out),
+                                  _stream(stream)), "dot_noalloc")
     return out
 
 

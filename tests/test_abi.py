@@ -123,3 +123,18 @@ def test_workspace_queries_scale(lib):
     assert lib.mpk_spmv_workspace_bytes(ctypes.byref(small), 1, 1) > 5000 * 16
     assert lib.mpk_dot_workspace_bytes(1000, 0, 2) >= 4 * 2 * 8
 
+
+def test_noalloc_dot_limits(lib):
+    """The inner product without workspace: its size limit is a pure host
+    query, and sizes past it are rejected before any device work."""
+    for C in (0, 1):
+        for p in (1, 2, 3, 4):
+            m = lib.mpk_dot_noalloc_max_elements(C, p)
+            assert m == (1 << 19) // ((2 if C else 1) * p) * 256
+            assert lib.mpk_dot_noalloc(p, C, m + 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                       ctypes.c_void_p(8), None) == -3
+    assert lib.mpk_dot_noalloc_max_elements(0, 5) == 0
+    assert lib.mpk_dot_noalloc(2, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                               ctypes.c_void_p(8), None) == -1
+    assert lib.mpk_dot_noalloc(2, 0, 10, None, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                               None) == -1

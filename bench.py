@@ -47,6 +47,8 @@ def apply_bytes(n, nnz, C, K, KF):
 
 
 def time_events(fn, reps, stream):
+    """Mean duration of fn over reps back-to-back launches (HIP events on
+    the stream the kernels run on)."""
     import torch
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -58,6 +60,35 @@ def time_events(fn, reps, stream):
         stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def time_events_cold(fn, reps, stream, flush):
+    """Mean duration of fn when a buffer larger than the 256 MiB Infinity
+    Cache has been written just before each launch, so that its inputs
+    come from HBM rather than from the cache."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        fn()
+        for a, b in evs:
+            flush.add_(1.0)
+            a.record(stream)
+            fn()
+            b.record(stream)
+    evs[-1][1].synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / reps
+
+
+def kernel_sources_digest():
+    """Digest of the sources of the measured kernels: hardware-counter
+    traffic recorded for another version of them is not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "mp.hpp", "internal.hpp", "ops.hip", "analysis.cpp"):
+        with open(os.path.join(ROOT, "paper_2504_14498_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(p, b, iters_gpu, passes):
@@ -86,21 +117,39 @@ def _gen_system(q):
     return p.n, p.row_ptr, p.col_idx, p.val, p.x_true
 
 
-def bench_batched(args):
+# vector streams of one BiCGSTAB pass beyond its two SpMVs and two applies
+# (loads and stores of n-element vectors by the update and inner-product
+# kernels)
+BICGSTAB_VECTOR_STREAMS = 17
+
+
+def batched_bytes(ns, nnzs, iters, K=2, KF=1):
+    """Algorithmic bytes of the batched solve: per system the ILU(0)
+    factorisation (A's values and indices read, the factor written) and,
+    per pass, two SpMVs, two ILU(0) applies and the vector streams."""
+    tot = 0
+    for n, nnz, it in zip(ns, nnzs, iters):
+        fac = nnz * (8 + 4) + 4 * (n + 1) + nnz * 8 * KF
+        per = (2 * spmv_bytes(n, nnz, 1, K) + 2 * apply_bytes(n, nnz, 1, K, KF)
+               + BICGSTAB_VECTOR_STREAMS * n * 8 * K)
+        tot += fac + it * per
+    return tot
+
+
+def measure_batched(nsys, warmup, steps, seq_sample, note):
     """512 random nonsymmetric systems (n ~ U{2000..200000}, 7-30 entries per
     row, diagonal dominance U(1.05, 2)) solved by ILU(0)-BiCGSTAB in DD to
     1e-25 in one persistent launch; compared with the same systems solved
-    one after another on the single-system path (a sample, scaled)."""
+    one after another on the single-system path (a sample, scaled by nnz)."""
     import concurrent.futures as cf
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:
-        systems = list(pool.map(_gen_system, range(args.nsys)))
+        systems = list(pool.map(_gen_system, range(nsys)))
     tgen = time.perf_counter() - t0
     import torch
 
     from paper_2504_14498_amd import mpk
     torch.cuda.set_device(0)
-    note = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
     note("generated %d systems in %.1f s: sum n = %d, sum nnz = %d" %
          (len(systems), tgen, sum(s[0] for s in systems), sum(len(s[2]) for s in systems)))
     mats, bs = [], []
@@ -110,21 +159,20 @@ def bench_batched(args):
         xt[:, 0, 0] = torch.as_tensor(x, device="cuda")
         mats.append(A)
         bs.append(mpk.csr_spmv(A, xt))
-        if len(mats) % 64 == 0:
+        if len(mats) % 128 == 0:
             note("uploaded %d systems: %.1f s" % (len(mats), time.perf_counter() - t0))
     del systems
     torch.cuda.synchronize()
     note("uploaded, b = A x_true computed: %.1f s" % (time.perf_counter() - t0))
     ws = None
-    for w in range(max(args.warmup, 1)):   # first call also autotunes the schedule
+    for w in range(max(warmup, 1)):   # the first call also autotunes the schedule
         a = time.perf_counter()
         xs, infos, st, ws = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25,
                                                      max_iter=10000, workspace=ws)
-        note("warmup %d (%s): %s, %.3f s (library setup %.1f ms, solve %.1f ms)" %
-             (w, "with autotune" if w == 0 else "tuned", st, time.perf_counter() - a,
-              infos[0]["setup_ms"], infos[0]["solve_ms"]))
+        note("batched warmup %d (%s): %s, %.3f s" %
+             (w, "with autotune" if w == 0 else "tuned", st, time.perf_counter() - a))
     times = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         torch.cuda.synchronize()
         a = time.perf_counter()
         xs, infos, st, ws = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25,
@@ -134,8 +182,7 @@ def bench_batched(args):
         note("batched solve: %s %.3f s" % (st, times[-1]))
     iters = [i["iters"] for i in infos]
     ok = sum(i["status"] == "ok" for i in infos)
-    # sequential sample on the single-system path
-    samp = list(range(0, len(mats), max(1, len(mats) // args.seq_sample)))[: args.seq_sample]
+    samp = list(range(0, len(mats), max(1, len(mats) // seq_sample)))[:seq_sample]
     tseq = 0.0
     nnz_s = 0
     for q in samp:
@@ -146,51 +193,60 @@ def bench_batched(args):
         torch.cuda.synchronize()
         tseq += time.perf_counter() - a
         nnz_s += mats[q].nnz
-        note("sequential system %d (n=%d): %s, %d iterations" % (q, mats[q].n, info["status"],
-                                                                 info["iters"]))
     tot_nnz = sum(A.nnz for A in mats)
     seq_proj = tseq * tot_nnz / max(nnz_s, 1)
     med = sorted(times)[len(times) // 2]
+    nbytes = batched_bytes([A.n for A in mats], [A.nnz for A in mats], iters)
+    gbs = nbytes / med / 1e9
+    return {"workload": "batched_random_dd nsys=%d (n ~ U{2000..200000}, 7-30 entries/row, "
+                        "BiCGSTAB-DD, ILU(0)-D, 1e-25)" % len(mats),
+            "sum_n": sum(A.n for A in mats), "sum_nnz": tot_nnz,
+            "launch_s": med, "solves_per_s": len(mats) / med, "converged": ok,
+            "iters_median": sorted(iters)[len(iters) // 2], "iters_max": max(iters),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nbytes},
+            "sequential": {"sample_systems": len(samp), "sample_s": tseq,
+                           "projected_s": seq_proj, "speedup": seq_proj / med}}
+
+
+def bench_batched(args):
+    note = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    r = measure_batched(args.nsys, args.warmup, args.steps, args.seq_sample, note)
     out = {"metric": "batched DD time-to-solution at rel. residual 1e-25 (ILU(0)-BiCGSTAB, "
                      "one persistent launch)",
-           "value": med, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": med * 1e3, "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "dd (2 x f64)",
+           "value": r["launch_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["launch_s"] * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "dd (2 x f64)",
            "data": "synthetic (seeded random diagonally dominant systems)",
-           "config": {"workload": "batched_random_dd nsys=%d" % len(mats),
-                      "sum_n": sum(A.n for A in mats), "sum_nnz": tot_nnz},
-           "converged": ok, "iters_median": sorted(iters)[len(iters) // 2],
-           "iters_max": max(iters), "solves_per_s": len(mats) / med,
-           "sequential": {"sample_systems": len(samp), "sample_s": tseq,
-                          "projected_s": seq_proj, "speedup": seq_proj / med}}
+           "config": {"workload": r["workload"]}, "batched": r}
     print(json.dumps(out))
 
 
-def bench_learned(args):
-    """Learned ILU(0) correction on the lognormal convection-diffusion
-    family (512^2, n = 262,144): train the network on method-generated
-    systems (streamed: each is factored, probed and used for one step),
+PARAMS_FILE = os.path.join(ROOT, "paper_2504_14498_amd", "learned_params.npz")
+
+
+def load_params(path):
+    """Kept network parameters and their training record (plain arrays,
+    loaded without unpickling)."""
+    saved = np.load(path, allow_pickle=False)
+    return saved["params"].astype(np.float32), json.loads(str(saved["train_info"]))
+
+
+def train_learned(args, note):
+    """Train the network on method-generated lognormal convection-diffusion
+    systems (streamed: each is factored, probed and used for one step) and
     keep the parameters that the plain method judges best on a validation
-    split, then compare DD BiCGSTAB time-to-solution at 1e-25, learned
-    (factor + network + correction + solve, fallbacks included) against
-    plain ILU(0), over held-out systems."""
+    split.  Returns (params on the device, training record)."""
     import concurrent.futures as cf
 
-    import numpy as np
     import torch
 
     from paper_2504_14498_amd import learned as LR
     from paper_2504_14498_amd import workloads as W
-
-    torch.cuda.set_device(0)
-    note = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
-    m = args.lgrid
-    ntrain, nval, ntest = args.ntrain, args.nval, args.ntest
+    m, ntrain, nval = args.lgrid, args.ntrain, args.nval
     gen = lambda s: W.config5(s, m=m)
     pool = cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    # validation split: the last nval training seeds, never trained on
-    val_seeds = list(range(ntrain - nval, ntrain))
+    val_seeds = list(range(ntrain - nval, ntrain))     # never trained on
     val = []
     for p in pool.map(gen, val_seeds):
         A = LR.mpk.Csr.from_problem(p)
@@ -203,7 +259,7 @@ def bench_learned(args):
     best = (1.0, tr.params.clone(), 0)     # delta = 0 is the plain factor
     losses = []
     t_train = time.perf_counter()
-    ntr = ntrain - nval if not args.load_params else 0
+    ntr = ntrain - nval
     for k, p in enumerate(pool.map(gen, range(ntr))):
         inst = LR.Instance(p, seed=k)
         losses.append(float(tr.step(inst)))
@@ -216,60 +272,84 @@ def bench_learned(args):
                 best = (r, tr.params.clone(), k + 1)
             note("step %d: validation iteration ratio %.3f (best %.3f at %d)"
                  % (k + 1, r, best[0], best[2]))
-    train_s = time.perf_counter() - t_train
-    params = best[1]
-    train_info = {"seconds": train_s, "steps": len(losses), "lr": args.lr, "kept_step": best[2],
-                  "validation_ratio": best[0],
-                  "loss_first_100": float(np.mean(losses[:100])) if losses else None,
-                  "loss_last_100": float(np.mean(losses[-100:])) if losses else None}
-    if args.load_params:
-        saved = np.load(args.load_params, allow_pickle=False)
-        params = torch.as_tensor(saved["params"]).cuda()
-        train_info = json.loads(str(saved["train_info"]))
-        note("loaded parameters from %s (trained %d steps)" % (args.load_params,
-                                                               train_info["steps"]))
-    if args.save_params:
-        np.savez(args.save_params, params=params.cpu().numpy(),
-                 train_info=np.array(json.dumps(train_info)))
-        note("saved parameters to %s" % args.save_params)
-    rows = []
-    if ntest == 0:
-        pool.shutdown()
-        print(json.dumps({"training": train_info, "validation_plain_iters": val_plain,
-                          "cap": cap}))
-        return
-    for q, p in enumerate(pool.map(gen, range(100_000, 100_000 + ntest))):
-        A = LR.mpk.Csr.from_problem(p)
-        b = LR.mpk.csr_spmv(A, torch.as_tensor(p.x_true_limbs(2)).cuda())
-        _, ip = LR.solve_plain(A, b)
-        _, il = LR.solve_learned(A, b, params, cap)
-        rows.append((ip["iters"], ip["tts_s"], il["iters_total"], il["tts_s"], il["fallback"],
-                     ip["status"], il["status"], il["relres_true"]))
-        if (q + 1) % 20 == 0:
-            note("test %d/%d: plain %d it %.3f s, learned %d it %.3f s" %
-                 (q + 1, ntest, rows[-1][0], rows[-1][1], rows[-1][2], rows[-1][3]))
     pool.shutdown()
+    info = {"seconds": time.perf_counter() - t_train, "steps": len(losses), "lr": args.lr,
+            "seed": args.seed, "grid": m, "train_seeds": [0, ntr - 1],
+            "validation_seeds": [val_seeds[0], val_seeds[-1]], "kept_step": best[2],
+            "validation_ratio": best[0], "validation_plain_iters": val_plain, "cap": cap,
+            "loss_first_100": float(np.mean(losses[:100])) if losses else None,
+            "loss_last_100": float(np.mean(losses[-100:])) if losses else None}
+    return best[1], info
+
+
+def evaluate_learned(params, cap, m, ntest, note):
+    """DD BiCGSTAB time-to-solution at 1e-25 over held-out systems (seeds
+    100000 + q), learned (factor + network + correction + solve, fallbacks
+    included) against plain ILU(0) on the same GPU."""
+    import concurrent.futures as cf
+
+    import torch
+
+    from paper_2504_14498_amd import learned as LR
+    from paper_2504_14498_amd import workloads as W
+    params = torch.as_tensor(params).cuda()
+    gen = lambda s: W.config5(s, m=m)
+    rows = []
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:
+        for q, p in enumerate(pool.map(gen, range(100_000, 100_000 + ntest))):
+            A = LR.mpk.Csr.from_problem(p)
+            b = LR.mpk.csr_spmv(A, torch.as_tensor(p.x_true_limbs(2)).cuda())
+            _, ip = LR.solve_plain(A, b)
+            _, il = LR.solve_learned(A, b, params, cap)
+            rows.append((ip["iters"], ip["tts_s"], il["iters_total"], il["tts_s"], il["fallback"],
+                         ip["status"], il["status"], il["relres_true"]))
+            if (q + 1) % 8 == 0:
+                note("learned test %d/%d: plain %d it %.3f s, learned %d it %.3f s" %
+                     (q + 1, ntest, rows[-1][0], rows[-1][1], rows[-1][2], rows[-1][3]))
     r = np.array([row[:4] for row in rows], dtype=np.float64)
-    fb = sum(row[4] is not None for row in rows)
-    ok = sum(row[5] == "ok" and row[6] == "ok" for row in rows)
-    med_l = float(np.median(r[:, 3]))
+    return {"workload": "lognormal_convdiff %dx%d (n = %d), BiCGSTAB-DD to 1e-25, held-out "
+                        "seeds 100000..%d" % (m, m, m * m, 100_000 + ntest - 1),
+            "test_systems": ntest, "cap": cap,
+            "plain": {"tts_s_quartiles": LR.quartiles(r[:, 1]),
+                      "iters_quartiles": LR.quartiles(r[:, 0])},
+            "learned": {"tts_s_quartiles": LR.quartiles(r[:, 3]),
+                        "iters_quartiles": LR.quartiles(r[:, 2]),
+                        "fallbacks": sum(row[4] is not None for row in rows)},
+            "median_ratio": {"tts": float(np.median(r[:, 3] / r[:, 1])),
+                             "iters": float(np.median(r[:, 2] / r[:, 0]))},
+            "both_converged": sum(row[5] == "ok" and row[6] == "ok" for row in rows),
+            "max_learned_relres_true": max(row[7] for row in rows)}
+
+
+def bench_learned(args):
+    """The learned workload on its own: train (or load) the parameters, then
+    compare learned and plain over the held-out systems."""
+    import torch
+    torch.cuda.set_device(0)
+    note = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if args.load_params:
+        params, info = load_params(args.load_params)
+        note("loaded parameters from %s (trained %d steps, kept step %d)" %
+             (args.load_params, info["steps"], info["kept_step"]))
+    else:
+        params, info = train_learned(args, note)
+        params = params.cpu().numpy()
+    if args.save_params:
+        np.savez(args.save_params, params=params, train_info=np.array(json.dumps(info)))
+        note("saved parameters to %s" % args.save_params)
+    if args.ntest == 0:
+        print(json.dumps({"training": info}))
+        return
+    r = evaluate_learned(params, info["cap"], args.lgrid, args.ntest, note)
+    med_l = r["learned"]["tts_s_quartiles"][1]
     out = {"metric": "DD time-to-solution at rel. residual 1e-25, learned vs plain ILU(0) "
                      "(BiCGSTAB, lognormal convection-diffusion)",
-           "value": med_l, "unit": "s", "n_gpus": 1, "steps": ntest, "warmup": nval,
+           "value": med_l, "unit": "s", "n_gpus": 1, "steps": args.ntest, "warmup": 0,
            "ms_per_step": med_l * 1e3, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "dd (2 x f64), network bf16/f32",
            "data": "synthetic (seeded lognormal-coefficient convection-diffusion)",
-           "config": {"workload": "lognormal_convdiff %dx%d" % (m, m), "n": m * m,
-                      "train_systems": ntrain - nval, "validation_systems": nval,
-                      "test_systems": ntest},
-           "learned": {"tts_s_quartiles": LR.quartiles(r[:, 3]),
-                       "iters_quartiles": LR.quartiles(r[:, 2]), "fallbacks": fb},
-           "plain": {"tts_s_quartiles": LR.quartiles(r[:, 1]),
-                     "iters_quartiles": LR.quartiles(r[:, 0])},
-           "median_ratio": {"tts": float(np.median(r[:, 3] / r[:, 1])),
-                            "iters": float(np.median(r[:, 2] / r[:, 0]))},
-           "both_converged": ok, "max_learned_relres_true": max(row[7] for row in rows),
-           "training": train_info,
+           "config": {"workload": r["workload"]}, "learned": r, "training": info,
            "total_s": time.perf_counter() - t0}
     print(json.dumps(out))
 
@@ -300,6 +380,10 @@ def main():
     ap.add_argument("--load-params", default=None, help="learned workload: skip training, load (.npz)")
     ap.add_argument("--nsys", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=8)
+    ap.add_argument("--learned-ntest", type=int, default=24,
+                    help="held-out systems of the learned comparison in the default run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline solve only (no batched and learned comparisons)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -388,12 +472,22 @@ def main():
     apply_gbs = ab / (apply_ms * 1e-3) / 1e9
     dominant = "ilu0_apply" if apply_ms >= spmv_ms else "spmv"
     dom_gbs, dom_bytes = (apply_gbs, ab) if dominant == "ilu0_apply" else (spmv_gbs, sb)
+    # the same kernels with their inputs coming from HBM: a buffer larger
+    # than the Infinity Cache is written before each launch
+    flush = torch.empty(512 << 17, dtype=torch.float64, device="cuda").zero_()
+    spmv_cold = time_events_cold(lambda: mpk.csr_spmv(A, b, y, stream=s), args.reps, s, flush)
+    apply_cold = time_events_cold(lambda: mpk.ilu0_apply(M, b, z, stream=s), args.reps, s, flush)
+    del flush
+    # HBM traffic per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    # recorded in profiles/traffic.json, only if they were taken on these
+    # kernel sources
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
         try:
             tr = json.load(open(tpath))
-            if tr.get("kernel") == dominant and tr.get("grid") == args.grid:
+            if (tr.get("kernel") == dominant and tr.get("grid") == args.grid
+                    and tr.get("sources") == kernel_sources_digest()):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -428,14 +522,37 @@ def main():
         "setup_ms": info["setup_ms"],
         "solve_ms": info["solve_ms"],
         "ms_per_iter": info["solve_ms"] / max(iters, 1),
-        "spmv": {"ms": spmv_ms, "gbs": spmv_gbs, "bytes": sb, "frac": spmv_gbs / HBM_PEAK_GBS},
+        "spmv": {"ms": spmv_ms, "gbs": spmv_gbs, "bytes": sb, "frac": spmv_gbs / HBM_PEAK_GBS,
+                 "note": "back to back: the 250 MB working set can stay in the 256 MiB "
+                         "Infinity Cache",
+                 "cold_ms": spmv_cold, "cold_gbs": sb / (spmv_cold * 1e-3) / 1e9,
+                 "cold_frac": sb / (spmv_cold * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "ilu0_apply": {"ms": apply_ms, "gbs": apply_gbs, "bytes": ab,
-                       "frac": apply_gbs / HBM_PEAK_GBS},
+                       "frac": apply_gbs / HBM_PEAK_GBS,
+                       "cold_ms": apply_cold, "cold_gbs": ab / (apply_cold * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": dom_bytes},
+                     "traffic": traffic, "traffic_source": "profiles/traffic.json (rocprofv3 "
+                     "FETCH_SIZE, WRITE_SIZE; null unless taken on these kernel sources)",
+                     "algorithmic_bytes": dom_bytes},
         "cpu_baseline": cpu,
     }
+    del M, y, z, ws, A, b, xt, x
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        # the batched and learned forms of the metric, on the same GPU
+        out["batched"] = measure_batched(args.nsys, 1, 1, args.seq_sample, note)
+        torch.cuda.empty_cache()
+        if os.path.exists(PARAMS_FILE):
+            params, tinfo = load_params(PARAMS_FILE)
+            lr = evaluate_learned(params, tinfo["cap"], tinfo["grid"], args.learned_ntest, note)
+            lr["training"] = {k: tinfo[k] for k in ("seconds", "steps", "kept_step", "seed",
+                                                   "lr", "validation_ratio", "cap")}
+            lr["params_file"] = os.path.relpath(PARAMS_FILE, ROOT)
+            out["learned"] = lr
+        else:
+            out["learned"] = None
+            note("no kept parameters at %s: learned comparison skipped" % PARAMS_FILE)
     print(json.dumps(out))
 
 

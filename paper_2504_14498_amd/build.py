@@ -23,9 +23,21 @@ FLAGS = [
 ]
 
 
+def _weight(name):
+    """Longest compiles first, so the parallel build is not held up by a
+    heavy unit started last."""
+    if name.startswith("krylov"):
+        return 0
+    if name.startswith("apply_") and name[-5] in "43":
+        return 1 if name[-5] == "4" else 2
+    if name.startswith("batched"):
+        return 3
+    return 4
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                  if f.endswith((".hip", ".cpp")))
+    names = [f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))]
+    return [os.path.join(CSRC, f) for f in sorted(names, key=lambda f: (_weight(f), f))]
 
 
 def _compile(src, verbose):

@@ -1,0 +1,7 @@
+// ILU(0) apply kernels for complex vectors of 1 limbs (see apply.hpp).
+#include "apply.hpp"
+
+namespace mpk {
+template int ilu0_apply_ck<2, 1>(const Ilu0 &, int, const double *, double *, int32_t *,
+                                  int32_t *, const int32_t *, hipStream_t);
+}

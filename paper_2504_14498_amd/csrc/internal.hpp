@@ -159,6 +159,10 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
 // Re-gather the sweep plans' values after the factor values in A's pattern
 // changed (same pattern).
 int ilu0_regather(const Ilu0 &M, hipStream_t s);
+// Defined in apply.hpp, instantiated for every (C, K) in apply_c<C>k<K>.hip.
+template <int C, int K>
+int ilu0_apply_ck(const Ilu0 &M, int conj, const double *r, double *z, int32_t *abort_reset,
+                  int32_t *abort_flag, const int32_t *done, hipStream_t s);
 int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z,
                       int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
                       hipStream_t s);

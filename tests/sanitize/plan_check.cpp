@@ -129,21 +129,6 @@ void check_plan(const HostCsr &h, const HostCsr &t, int kind, const HostPlan &p)
         for (int32_t q = s; q < e; ++q) start[q] = s;
       }
     EXPECT(p.max_piece >= 1 && p.max_piece <= BLOCK);
-    // block queues: every block once, each queue in sweep order
-    EXPECT(p.nq >= 1 && p.nq <= MAX_QUEUES && p.nq <= std::max(1, p.nblk));
-    EXPECT(p.blk_q.size() == size_t(p.nblk) + p.nq + 1);
-    EXPECT(p.blk_q[p.nblk] == 0 && p.blk_q[p.nblk + p.nq] == p.nblk);
-    std::vector<char> seen(size_t(p.nblk), 0);
-    for (int32_t q = 0; q < p.nq; ++q) {
-      const int32_t a = p.blk_q[p.nblk + q], e = p.blk_q[p.nblk + q + 1];
-      EXPECT(a <= e);
-      for (int32_t k = a; k < e; ++k) {
-        const int32_t b = p.blk_q[k];
-        EXPECT(b >= 0 && b < p.nblk && !seen[b]);
-        seen[b] = 1;
-        EXPECT(k == a || p.blk_q[k - 1] < b);
-      }
-    }
   }
   for (int64_t i = 0; i < n; ++i)
     deps(h, t, kind, i, [&](int32_t j) {

@@ -462,6 +462,8 @@ size_t plan_bytes(int64_t n, int64_t nnz_bound, int C, int KF, bool div, Bump &b
   p.blk_r = b.take<int32_t>(2 * size_t(n) + 2);
   p.blk_lev = b.take<int32_t>(size_t(n) + 1);
   p.loc_pos = b.take<int32_t>(size_t(n) + 1);
+  p.xflag = b.take<int32_t>(size_t(n) + 1);
+  p.xlist = b.take<int32_t>(size_t(n) + 1);
   p.div = div;
   return b.off;
 }

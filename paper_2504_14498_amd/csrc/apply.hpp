@@ -29,13 +29,13 @@ inline void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *
       hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, WAVE>), dim3(grid ? grid : 1),
                          dim3(WAVE), lds, s, P.n, P.ptr, P.col, P.val, P.dval, P.blk_r,
                          P.blk_lev, P.loc_pos, P.nblk, P.ell_col, P.ell_meta,
-                         P.ell_val, P.blk_rows, rhs, out, P.sync,
+                         P.ell_val, P.blk_rows, P.geom.P, P.geom.w, P.geom.t, rhs, out, P.sync,
                          abort_flag, done);
     else
       hipLaunchKernelGGL((trsv_blocked<C, K, KF, DIV, CONJ, BLOCK>), dim3(grid ? grid : 1),
                          dim3(BLOCK), lds, s, P.n, P.ptr, P.col, P.val, P.dval, P.blk_r,
                          P.blk_lev, P.loc_pos, P.nblk, P.ell_col, P.ell_meta,
-                         P.ell_val, P.blk_rows, rhs, out, P.sync,
+                         P.ell_val, P.blk_rows, P.geom.P, P.geom.w, P.geom.t, rhs, out, P.sync,
                          abort_flag, done);
     return;
   }
@@ -58,10 +58,14 @@ inline int apply_ckf(const Ilu0 &M, int conj, const double *r, double *z, int32_
                      int32_t *abort_flag, const int32_t *done, hipStream_t s) {
   const Plan &P1 = conj ? M.UH : M.L;
   const Plan &P2 = conj ? M.LH : M.U;
-  const int64_t words = M.n * C * K;
-  const int64_t cover = std::max<int64_t>(words, std::max(P1.nlev, P2.nlev));
-  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(cover)), dim3(BLOCK), 0, s, words, M.tmp, z, P1.nlev,
-                     P1.lev_done, P2.nlev, P2.lev_done, P1.sync, P2.sync, abort_reset, done);
+  // blocked sweeps poll only the rows other blocks read; level sweeps poll
+  // every row
+  const int32_t *l1 = P1.mode == 1 ? P1.xlist : nullptr, *l2 = P2.mode == 1 ? P2.xlist : nullptr;
+  const int64_t c1 = P1.mode == 1 ? P1.nx : M.n, c2 = P2.mode == 1 ? P2.nx : M.n;
+  const int64_t cover = std::max<int64_t>(std::max(c1, c2) * C * K, std::max(P1.nlev, P2.nlev));
+  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(std::max<int64_t>(cover, 1))), dim3(BLOCK), 0, s,
+                     C * K, l1, c1, M.tmp, l2, c2, z, P1.nlev, P1.lev_done, P2.nlev, P2.lev_done,
+                     P1.sync, P2.sync, abort_reset, done);
   if (!conj) {
     launch_trsv<C, K, KF, false, false>(P1, r, M.tmp, abort_flag, done, s);
     launch_trsv<C, K, KF, true, false>(P2, M.tmp, z, abort_flag, done, s);

@@ -121,6 +121,13 @@ struct Plan {
   int32_t *blk_r = nullptr;    // [2*nblk] first range [r0, r1) of each block
   int32_t *blk_lev = nullptr;  // [nblk+1] first local level of each block
   int32_t *loc_pos = nullptr;  // [nloc+1] first position of each local level
+  // rows that rows of other blocks read from memory (blocked schedule):
+  // the only ones polled, so the only ones given the sentinel and stored
+  // as soon as they are finished; the other rows reach memory when their
+  // block ends
+  int32_t *xflag = nullptr;    // [n] 1 if read by another block
+  int32_t *xlist = nullptr;    // [nx] those rows
+  int64_t nx = 0;
   // flat per-position dependency slots (blocked schedule): up to ELLW
   // dependencies of the row at position pos live at [pos * ELLW + d]
   int32_t *ell_nd = nullptr;   // [n] dependencies of each position

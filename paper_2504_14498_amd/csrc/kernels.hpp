@@ -6,12 +6,13 @@
 namespace mpk {
 
 // ------------------------------------------------------------ reductions
-// Fixed-order reduction of ND element sums over a 256-thread workgroup:
-// xor-butterfly inside each wavefront, then wavefronts 0..3 in order.
-// The result is a deterministic function of the inputs (no atomics).
-template <int C, int K, int ND>
+// Fixed-order reduction of ND element sums over a workgroup of NT threads
+// (256 unless stated): xor-butterfly inside each wavefront, then the
+// wavefronts in order.  The result is a deterministic function of the
+// inputs (no atomics).
+template <int C, int K, int ND, int NT = BLOCK>
 __device__ __forceinline__ void block_reduce(el<C, K> (&d)[ND], double *out) {
-  __shared__ double red[BLOCK / WAVE][ND > 0 ? ND : 1][C * K];
+  __shared__ double red[NT / WAVE][ND > 0 ? ND : 1][C * K];
 #pragma unroll
   for (int off = WAVE / 2; off >= 1; off >>= 1) {
 #pragma unroll
@@ -37,7 +38,7 @@ __device__ __forceinline__ void block_reduce(el<C, K> (&d)[ND], double *out) {
 #pragma unroll
     for (int q = 0; q < ND; ++q) {
       el<C, K> s = el_load<C, K>(red[0][q]);
-      for (int ww = 1; ww < BLOCK / WAVE; ++ww) s = el_add<C, K>(s, el_load<C, K>(red[ww][q]));
+      for (int ww = 1; ww < NT / WAVE; ++ww) s = el_add<C, K>(s, el_load<C, K>(red[ww][q]));
       if (out) el_store<C, K>(out + size_t(q) * C * K, s);
       d[q] = s;
     }
@@ -270,14 +271,17 @@ static __global__ void scan_add(int64_t n, int32_t *out, const int32_t *__restri
 // A flat slot holds the column j of a dependency in another block, or
 // -(LDS slot of j + 1) for one in the row's own block (geometry G); each
 // position's row, dependency count and own LDS slot go to one 16-byte
-// record of ell_meta, fetched with a single load.
+// record of ell_meta, fetched with a single load.  xflag (blocked
+// schedules, zeroed before) marks every row that a row of another block
+// depends on; plan_xmeta copies the mark into the record's last word.
 static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                  const int32_t *__restrict__ srcmap, int lower,
                                  const int32_t *__restrict__ ptr, int32_t *col, int32_t *src,
                                  int32_t *ell_nd, int32_t *ell_col, int32_t *ell_src,
                                  int32_t *ell_meta, BlockGeom G,
-                                 const int32_t *__restrict__ diag, int32_t *dsrc) {
+                                 const int32_t *__restrict__ diag, int32_t *dsrc,
+                                 int32_t *xflag) {
   const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   if (pos >= n) return;
   const int32_t i = order[pos];
@@ -298,6 +302,7 @@ static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
         ell_col[pos * ELLW + d] = G.block(j) == bi ? -(G.slot(j) + 1) : j;
         ell_src[pos * ELLW + d] = sp;
       }
+      if (xflag && G.block(j) != bi) atomicOr(&xflag[j], 1);
       ++o;
       ++d;
     }
@@ -311,6 +316,21 @@ static __global__ void plan_fill(int64_t n, const int32_t *__restrict__ order,
     }
   }
   if (dsrc) dsrc[pos] = diag[i];
+}
+
+// The last word of each position's record: whether a row of another block
+// reads this row from memory.
+static __global__ void plan_xmeta(int64_t n, const int32_t *__restrict__ order,
+                                  const int32_t *__restrict__ xflag, int32_t *ell_meta) {
+  const int64_t pos = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (pos < n) ell_meta[pos * 4 + 3] = xflag[order[pos]];
+}
+
+// Rows with xflag set, in ascending order, at their exclusive-scan offsets.
+static __global__ void plan_xlist(int64_t n, const int32_t *__restrict__ xflag,
+                                  const int32_t *__restrict__ off, int32_t *xlist) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i < n && xflag[i]) xlist[off[i]] = int32_t(i);
 }
 
 // ------------------------------------------------------ ILU(0) factor
@@ -587,6 +607,7 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, d
 
 template <int C, int K, int KF, int MAXD> struct RowPre {
   int32_t i, pos, nd, slot;
+  int32_t x;           // read by a row of another block: stored at once
   bool valid;
   // flat slots: column j, or -(LDS slot + 1) inside the block; one 4-word
   // vector, as loaded, so the prefetch stages keep it in one register tuple
@@ -616,6 +637,7 @@ __device__ __forceinline__ void row_fetch_meta(RowPre<C, K, KF, MAXD> &r, int32_
   r.i = int32_t(m.x);
   r.nd = int32_t(m.y);
   r.slot = int32_t(m.z);
+  r.x = int32_t(m.w);
   r.cj = __builtin_bit_cast(bi4, __builtin_amdgcn_raw_buffer_load_b128(
                                      B.col, int(valid ? uint32_t(pos) * 4u * ELLW : BUF_OOB), 0, 0));
   const uint32_t fo = valid ? uint32_t(pos) * uint32_t(ELLW * C * KF * 8) : BUF_OOB;
@@ -705,7 +727,7 @@ __device__ __forceinline__ void wait_ext(RowPre<C, K, KF, MAXD> &r, int32_t pe, 
 
 // Finish one row: acc = rhs_i (prefetched with the external values) minus the
 // products in ascending column order, divided by the pivot when DIV; the
-// result goes to the row's LDS slot and to out.  A lane without a row uses
+// result goes to the row's LDS slot, and to out if another block reads it.  A lane without a row uses
 // the spare LDS slot `spare` and an out-of-range store.  Dependencies past
 // the ELLW flat slots come from the CSR arrays; the host allows them only
 // for blocks of one range [r0, r1), where row j sits in slot j - r0.
@@ -770,7 +792,9 @@ __device__ __forceinline__ void row_finish(RowPre<C, K, KF, MAXD> &r, const int3
     }
   }
   if constexpr (DIV) acc = el_div_k<C, K, KF>(acc, r.dv);
-  const uint32_t oo = r.valid ? uint32_t(r.i) * uint32_t(E * 8) : BUF_OOB;
+  // only rows that other blocks poll are stored now; the block's other
+  // results reach memory when the block ends (trsv_blocked's flush)
+  const uint32_t oo = (r.valid && r.x) ? uint32_t(r.i) * uint32_t(E * 8) : BUF_OOB;
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -802,9 +826,11 @@ template <int E> constexpr int trsv_depth() { return E <= 2 ? 6 : 3; }
 template <int E> constexpr int trsv_lead() { return E <= 2 ? 2 : 1; }
 
 // Blocked sweep: a workgroup takes the next block (in sweep order; its
-// rows and their LDS slots come from the plan, see BlockGeom) and walks the
-// block's local levels (each at most NT rows: one per lane), separated by
-// LDS-only barriers.  A row's right-hand side is prefetched with its
+// rows and their LDS slots come from the plan, see BlockGeom: ranges of
+// gw-slot width, gt of them, gP rows apart) and walks the block's local
+// levels (each at most NT rows: one per lane), separated by LDS-only
+// barriers; rows that other blocks read are stored as they are finished,
+// and at the end the whole block is copied from LDS to out.  A row's right-hand side is prefetched with its
 // external values; in-block results are kept in LDS for the rows that need
 // them, and values of other blocks are read from out with the
 // sentinel-checked wait.  blk_r holds the first range [r0, r1) of each
@@ -824,7 +850,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int32_t *__restrict__ blk_r, const int32_t *__restrict__ blk_lev,
     const int32_t *__restrict__ loc_pos, int32_t nblk, const int32_t *__restrict__ ell_col,
     const int32_t *__restrict__ ell_meta, const double *__restrict__ ell_val, int32_t spare,
-    const double *__restrict__ rhs, double *out,
+    int64_t gP, int32_t gw, int32_t gt, const double *__restrict__ rhs, double *out,
     int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
   if (done && *done) return;
   extern __shared__ double lds[];
@@ -882,25 +908,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 #pragma unroll
       for (int u = 0; u < D; ++u) stage(st[u], st[(u + X) % D], lv + u);
     }
+    // the block's results from LDS to out, range by range: range k holds
+    // rows r0 + k P + c in LDS slots k w + c, and consecutive lanes store
+    // consecutive rows
+    lds_barrier<NT>();
+    const int32_t wb = r1 - r0;
+    for (int32_t k = 0; k < gt; ++k) {
+      const int64_t a = int64_t(r0) + int64_t(k) * gP;
+      if (a >= n) break;
+      const int32_t cnt = int32_t(min<int64_t>(wb, n - a));
+      for (int32_t c = tid; c < cnt; c += NT) {
+        const double *src = lds + size_t(k * gw + c) * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf_st(B.out, uint32_t((a + c) * E + e) * 8u, src[e]);
+      }
+    }
     __syncthreads();
   }
 }
 
-// Prepares one apply: outputs filled with SENTINEL, the per-level counters
-// zeroed and the two tickets reset (a kernel rather than a memset, so the
-// step can be graph-captured).  The abort word is reset only when
-// abort_reset is non-null: inside a solve it persists so the host sees any
-// watchdog event at the end.
-static __global__ void trsv_prep(int64_t words, double *out1, double *out2, int32_t nlev1,
-                                 int32_t *lev1, int32_t nlev2, int32_t *lev2, int32_t *ticket1,
-                                 int32_t *ticket2, int32_t *abort_reset, const int32_t *done) {
+// Prepares one apply: the words that other workgroups poll filled with
+// SENTINEL (rows list1[0..cnt1) of out1 and list2[0..cnt2) of out2, or
+// rows 0..cnt-1 when a list is null: the level schedule polls every row),
+// the per-level counters zeroed and the two tickets reset (a kernel rather
+// than a memset, so the step can be graph-captured).  The abort word is
+// reset only when abort_reset is non-null: inside a solve it persists so
+// the host sees any watchdog event at the end.
+static __global__ void trsv_prep(int E, const int32_t *__restrict__ list1, int64_t cnt1,
+                                 double *out1, const int32_t *__restrict__ list2, int64_t cnt2,
+                                 double *out2, int32_t nlev1, int32_t *lev1, int32_t nlev2,
+                                 int32_t *lev2, int32_t *ticket1, int32_t *ticket2,
+                                 int32_t *abort_reset, const int32_t *done) {
   if (done && *done) return;
   const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
   const double sent = __builtin_bit_cast(double, (unsigned long long)SENTINEL);
-  if (i < words) {
-    out1[i] = sent;
-    out2[i] = sent;
-  }
+  const int64_t q = i / E, e = i - q * E;
+  if (q < cnt1) out1[(list1 ? int64_t(list1[q]) : q) * E + e] = sent;
+  if (q < cnt2) out2[(list2 ? int64_t(list2[q]) : q) * E + e] = sent;
   if (i < nlev1) lev1[i] = 0;
   if (i < nlev2) lev2[i] = 0;
   if (i == 0) {

@@ -103,16 +103,32 @@ static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
   hipLaunchKernelGGL(scan_add, dim3(g), dim3(BLOCK), 0, s, n, P.ptr, (const int32_t *)M.scan_tmp,
                      nb);
   const bool ell = P.mode == 1;
+  if (ell) MPK_HIP(hipMemsetAsync(P.xflag, 0, sizeof(int32_t) * size_t(n), s));
   hipLaunchKernelGGL(plan_fill, dim3(g), dim3(BLOCK), 0, s, n, P.order, rp, ci,
                      tr ? (const int32_t *)M.t_src : nullptr, lower, (const int32_t *)P.ptr, P.col,
                      P.src, ell ? P.ell_nd : nullptr, ell ? P.ell_col : nullptr,
                      ell ? P.ell_src : nullptr, ell ? P.ell_meta : nullptr, P.geom,
-                     (const int32_t *)M.diag, P.div ? P.dsrc : nullptr);
+                     (const int32_t *)M.diag, P.div ? P.dsrc : nullptr, ell ? P.xflag : nullptr);
+  if (ell) {
+    // the rows other blocks read: marked in the records, and listed (their
+    // scan offsets go to lev_done, which only the level schedule uses)
+    hipLaunchKernelGGL(plan_xmeta, dim3(g), dim3(BLOCK), 0, s, n, (const int32_t *)P.order,
+                       (const int32_t *)P.xflag, P.ell_meta);
+    hipLaunchKernelGGL(scan_blocks, dim3(nb), dim3(BLOCK), 0, s, n, (const int32_t *)P.xflag,
+                       P.lev_done, M.scan_tmp);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(BLOCK), 0, s, nb, M.scan_tmp);
+    hipLaunchKernelGGL(scan_add, dim3(g), dim3(BLOCK), 0, s, n, P.lev_done,
+                       (const int32_t *)M.scan_tmp, nb);
+    hipLaunchKernelGGL(plan_xlist, dim3(g), dim3(BLOCK), 0, s, n, (const int32_t *)P.xflag,
+                       (const int32_t *)P.lev_done, P.xlist);
+  }
   MPK_HIP(hipGetLastError());
-  int32_t tot = 0;
-  MPK_HIP(hipMemcpyAsync(&tot, P.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t tot[2] = {0, 0};
+  MPK_HIP(hipMemcpyAsync(&tot[0], P.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (ell) MPK_HIP(hipMemcpyAsync(&tot[1], P.lev_done + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MPK_HIP(hipStreamSynchronize(s));
-  P.nnz = tot;
+  P.nnz = tot[0];
+  P.nx = ell ? tot[1] : n;
   return MPK_OK;
 }
 

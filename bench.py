@@ -87,7 +87,7 @@ def kernel_sources_digest():
     traffic recorded for another version of them is not reported."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "mp.hpp", "internal.hpp", "ops.hip", "analysis.cpp"):
+    for f in ("kernels.hpp", "mp.hpp", "internal.hpp", "ops.hip", "apply.hpp", "analysis.cpp"):
         with open(os.path.join(ROOT, "paper_2504_14498_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -896,13 +896,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __syncthreads();
     // one local level: finish `now`; then request the external values of
     // level l+X (slot `ext`, whose indices arrived D-X stages ago) and
-    // refill `now` with the row data of level l+D
+    // refill `now` with the row data of level l+D.  The refill's level
+    // bounds come from vector loads issued one stage earlier (all lanes,
+    // one address): a scalar load would make every LDS wait of the next
+    // level wait for it too, since the two share a counter.
+    const __amdgpu_buffer_rsrc_t lp = buf_rsrc(loc_pos, (l1 + 1) * 4);
+    auto lp_ld = [&](int32_t l) {
+      return int32_t(__builtin_amdgcn_raw_buffer_load_b32(lp, min(l, l1) * 4, 0, 0));
+    };
+    int32_t vb = lp_ld(l0 + D), ve = lp_ld(l0 + D + 1);
     auto stage = [&](RP &now, RP &ext, int32_t l) {
       row_finish<C, K, KF, DIV, CONJ, MAXD>(now, ptr, col, val, out, B, lds, r0, r1, spare,
                                             abort_flag);
       lds_barrier<NT>();
       row_fetch_ext<C, K, KF, MAXD>(ext, B);
-      meta(now, l + D);
+      row_fetch_meta<C, K, KF, DIV, CONJ, MAXD>(now, vb + tid, vb + tid < ve, B);
+      vb = ve;
+      ve = lp_ld(l + D + 2);
     };
     for (int32_t lv = l0; lv < l1; lv += D) {
 #pragma unroll

@@ -1091,61 +1091,113 @@ static void record(double *hist, int64_t hist_len, int64_t k, double nr2)
         hist[k - 1] = nr2;
 }
 
-/* Preconditioned BiCG, Algorithm 3. */
+/* Preconditioned BiCG (the method that Algorithm 3 states), written from
+ * its defining recurrences.  BiCG builds two coupled sequences, one for A
+ * (residuals r_k = b - A x_k) and one for A^H (shadow residuals s_k, with
+ * s_0 = r_0), kept biorthogonal through M: <M^-H s_j, r_k> = 0 for j != k.
+ * A pass of the pair:
+ *   images       (q, q~) = (A d, A^H d~) of the search directions;
+ *   step length  alpha = rho / <d~, q>, rho = <M^-H s, r>;
+ *   advance      x += alpha d,  r -= alpha q,  s -= conj(alpha) q~;
+ *   directions   (z, z~) = (M^-1 r, M^-H s), rho' = <z~, r>,
+ *                beta = rho' / rho,  d = z + beta d,  d~ = z~ + conj(beta) d~.
+ * The vector operations are the oracle's element-wise ones; each is one
+ * pass over the rows, so a pass's rounding does not depend on the order in
+ * which independent vectors are updated. */
+typedef struct {
+    double *r, *s;     /* residual and shadow residual */
+    double *z, *zs;    /* their preconditioned forms */
+    double *d, *ds;    /* search directions */
+    double *q, *qs;    /* images of the directions */
+    double rho[2 * KMAX];
+} bicg_pair_t;
+
+static void bicg_pair_init(const sys_t *s, bicg_pair_t *P, const double *b, const double *x)
+{
+    double *ax = vnew(s);
+    P->r = vnew(s); P->s = vnew(s); P->z = vnew(s); P->zs = vnew(s);
+    P->d = vnew(s); P->ds = vnew(s); P->q = vnew(s); P->qs = vnew(s);
+    matvec(s, x, ax);
+    v_sub(s, b, ax, P->r);
+    vcopy(s, P->r, P->s);
+    precond(s, P->r, P->z);
+    precond_h(s, P->s, P->zs);
+    vcopy(s, P->z, P->d);
+    vcopy(s, P->zs, P->ds);
+    dot(s, P->zs, P->r, P->rho);
+    free(ax);
+}
+
+static void bicg_pair_free(bicg_pair_t *P)
+{
+    free(P->r); free(P->s); free(P->z); free(P->zs);
+    free(P->d); free(P->ds); free(P->q); free(P->qs);
+}
+
+/* Images of the directions and the step length; 0 on breakdown (a zero
+ * <d~, q> or rho). */
+static int bicg_step_length(const sys_t *s, bicg_pair_t *P, double *alpha)
+{
+    double dq[2 * KMAX];
+    matvec(s, P->d, P->q);
+    or_spmv_h(s->n, s->rp, s->ci, s->val, s->C, s->K, P->ds, P->qs);
+    dot(s, P->ds, P->q, dq);
+    if (is_zero(s, dq) || is_zero(s, P->rho))
+        return 0;
+    el_div(s->C, s->K, P->rho, dq, alpha);
+    return 1;
+}
+
+static void bicg_advance(const sys_t *s, bicg_pair_t *P, const double *alpha, double *x)
+{
+    double ca[2 * KMAX];
+    v_axpy(s, x, alpha, P->d, x);
+    v_axmy(s, P->r, alpha, P->q, P->r);
+    el_conj(s->C, s->K, alpha, ca);
+    v_axmy(s, P->s, ca, P->qs, P->s);
+}
+
+static void bicg_new_directions(const sys_t *s, bicg_pair_t *P)
+{
+    double rho_next[2 * KMAX], beta[2 * KMAX], cb[2 * KMAX];
+    precond(s, P->r, P->z);
+    precond_h(s, P->s, P->zs);
+    dot(s, P->zs, P->r, rho_next);
+    el_div(s->C, s->K, rho_next, P->rho, beta);
+    v_axpy(s, P->z, beta, P->d, P->d);
+    el_conj(s->C, s->K, beta, cb);
+    v_axpy(s, P->zs, cb, P->ds, P->ds);
+    memcpy(P->rho, rho_next, sizeof(double) * s->E);
+}
+
 static int run_bicg(const sys_t *s, const double *b, double *x, int64_t max_iter,
                     double eps_r, double eps_a, or_info_t *info, double *hist, int64_t hlen)
 {
-    int E = s->E, C = s->C, K = s->K;
-    double *r = vnew(s), *rt = vnew(s), *z = vnew(s), *zt = vnew(s), *p = vnew(s),
-           *pt = vnew(s), *q = vnew(s), *qt = vnew(s), *tmp = vnew(s);
-    double rho[2 * KMAX], rho_new[2 * KMAX], alpha[2 * KMAX], beta[2 * KMAX], d[2 * KMAX],
-        ca[2 * KMAX], nr02, nr2 = 0;
+    bicg_pair_t P;
+    double alpha[2 * KMAX], nr02, nr2 = 0;
     int64_t k;
     int st = ST_NOT_CONVERGED;
-    matvec(s, x, tmp);
-    v_sub(s, b, tmp, r);
-    vcopy(s, r, rt);
-    nr02 = nrm2sq_hi(s, r);
-    precond(s, r, z);
-    precond_h(s, rt, zt);
-    vcopy(s, z, p);
-    vcopy(s, zt, pt);
-    dot(s, zt, r, rho);
+    bicg_pair_init(s, &P, b, x);
+    nr02 = nrm2sq_hi(s, P.r);
     info->iters = 0;
     for (k = 1; k <= max_iter; ++k) {
-        matvec(s, p, q);
-        or_spmv_h(s->n, s->rp, s->ci, s->val, C, K, pt, qt);
-        dot(s, pt, q, d);
-        if (is_zero(s, d) || is_zero(s, rho)) {
+        info->iters = k;
+        if (!bicg_step_length(s, &P, alpha)) {
             st = ST_BREAKDOWN;
-            info->iters = k;
             break;
         }
-        el_div(C, K, rho, d, alpha);
-        v_axpy(s, x, alpha, p, x);
-        v_axmy(s, r, alpha, q, r);
-        el_conj(C, K, alpha, ca);
-        v_axmy(s, rt, ca, qt, rt);
-        nr2 = nrm2sq_hi(s, r);
+        bicg_advance(s, &P, alpha, x);
+        nr2 = nrm2sq_hi(s, P.r);
         record(hist, hlen, k, nr2);
-        info->iters = k;
-        if (stop_test(nr2, nr02, eps_r, eps_a)) {
-            if (true_check(s, b, x, nr02, eps_r, eps_a, &info->relres_true)) {
-                st = ST_OK;
-                break;
-            }
+        if (stop_test(nr2, nr02, eps_r, eps_a) &&
+            true_check(s, b, x, nr02, eps_r, eps_a, &info->relres_true)) {
+            st = ST_OK;
+            break;
         }
-        precond(s, r, z);
-        precond_h(s, rt, zt);
-        dot(s, zt, r, rho_new);
-        el_div(C, K, rho_new, rho, beta);
-        v_axpy(s, z, beta, p, p);
-        el_conj(C, K, beta, ca);
-        v_axpy(s, zt, ca, pt, pt);
-        memcpy(rho, rho_new, sizeof(double) * E);
+        bicg_new_directions(s, &P);
     }
     info->relres_recursive = nr02 > 0 ? sqrt(nr2 / nr02) : sqrt(nr2);
-    free(r); free(rt); free(z); free(zt); free(p); free(pt); free(q); free(qt); free(tmp);
+    bicg_pair_free(&P);
     return st;
 }
 

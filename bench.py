@@ -211,6 +211,41 @@ def measure_batched(nsys, warmup, steps, seq_sample, note):
                            "projected_s": seq_proj, "speedup": seq_proj / med}}
 
 
+def measure_spmv_rows(reps, note):
+    """SpMV (DD vectors) on one system of the batched workload (random
+    columns, 7-30 entries per row): one lane per row against the vector
+    layouts (2-16 lanes per row), each timed with its inputs coming from
+    HBM, and the lanes the library's tuner picks."""
+    import torch
+
+    from paper_2504_14498_amd import mpk
+    from paper_2504_14498_amd import workloads as W
+    p = W.config4_system(0)
+    A = mpk.Csr.from_problem(p)
+    K = 2
+    x = torch.rand((p.n, 1, K), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    flush = torch.empty(512 << 17, dtype=torch.float64, device="cuda").zero_()
+    sb = spmv_bytes(p.n, p.nnz, 1, K)
+    cold = {}
+    for lanes in (1, 2, 4, 8, 16):
+        mpk.spmv_set_lanes(A, lanes)
+        cold[lanes] = time_events_cold(lambda: mpk.csr_spmv(A, x, y, stream=s), reps, s, flush)
+    mpk.spmv_set_lanes(A, 0)
+    tuned, _ = mpk.spmv_tune(A, x, y, stream=s)
+    del flush
+    note("spmv random rows: " + " ".join("%d:%.4f ms" % (l, t) for l, t in cold.items()) +
+         ", tuner picks %d" % tuned)
+    return {"workload": "random nonsymmetric n=%d nnz=%d (7-30 entries/row), DD vectors"
+                        % (p.n, p.nnz),
+            "bytes": sb, "note": "cold: a 512 MiB buffer read before each launch",
+            "cold_ms_by_lanes": {str(l): t for l, t in cold.items()},
+            "cold_gbs_by_lanes": {str(l): sb / (t * 1e-3) / 1e9 for l, t in cold.items()},
+            "tuned_lanes": tuned, "tuned_cold_ms": cold[tuned],
+            "speedup_tuned_vs_1": cold[1] / cold[tuned]}
+
+
 def bench_batched(args):
     note = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
     r = measure_batched(args.nsys, args.warmup, args.steps, args.seq_sample, note)
@@ -544,6 +579,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         # the batched and learned forms of the metric, on the same GPU
+        out["spmv_random_rows"] = measure_spmv_rows(args.reps, note)
+        torch.cuda.empty_cache()
         out["batched"] = measure_batched(args.nsys, 1, 1, args.seq_sample, note)
         torch.cuda.empty_cache()
         if os.path.exists(PARAMS_FILE):

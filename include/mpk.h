@@ -106,6 +106,21 @@ int mpk_dcsr_spmv(mpk_prec xp, const mpk_csr *A, int trans, const double *x, dou
 int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x, double *y,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* Lanes per row of the plain (non-transposed) SpMV for one matrix, keyed
+ * by its row_ptr, col_idx and val pointers and n: 1 = one lane per row
+ * (the default), 2, 4, 8 or 16 = vector CSR, where that many lanes load and
+ * multiply a row's entries (contiguous loads of indices and values) and
+ * then add the products in ascending column order.  y is identical for
+ * every choice.  0 forgets the choice.  Host-side only; MPK_EINVAL for
+ * other values. */
+int mpk_spmv_set_lanes(const mpk_csr *A, int lanes);
+/* Times y = A x on stream with each lanes-per-row choice (1, 2, 4, 8, 16:
+ * one warm-up launch, then three timed) and keeps the fastest for A; *lanes
+ * and *ms (either may be NULL) receive it and its mean time per launch.
+ * x and y as for mpk_?csr_spmv (y is overwritten).  Synchronous. */
+int mpk_spmv_tune(mpk_prec xp, const mpk_csr *A, int is_complex, const double *x, double *y,
+                  int *lanes, double *ms, void *stream);
+
 /* --------------------------------------------------------------- ILU(0)
  * ILU(0) factorisation (Algorithm 1) on the stored pattern of A, in factor
  * precision fp = MPK_D (binary64: the "_d_ILU(0)" factor of Section 4) or

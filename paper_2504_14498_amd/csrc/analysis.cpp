@@ -217,34 +217,69 @@ static BlockGeom deep_geom(const DepView &dv, int64_t n, int cap) {
   return g;
 }
 
+// Schedule of a sweep: blocked (mode 1) when at least half of the
+// dependencies stay inside blocks of blk_rows consecutive rows, else the
+// level schedule (mode 0).  One pass over the pattern on up to 8 host
+// threads.
+int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows) {
+  int mode = 0;
+  if (blk_rows > 0) {
+    const int64_t n = h.n;
+    const HostCsr &g = (kind >= 2) ? *ht : h;
+    const DepView dv{g.rp, g.ci, kind == 0 || kind == 2};
+    int shift = 0;
+    while ((int64_t(1) << shift) < blk_rows) ++shift;
+    const int T = int(std::min<int64_t>(8, std::max<int64_t>(1, n / 65536)));
+    std::vector<int64_t> internal(size_t(T), 0), total(size_t(T), 0);
+    auto work = [&](int t) {
+      const int64_t i0 = n * t / T, i1 = n * (t + 1) / T;
+      int64_t in = 0, tot = 0;
+      for (int64_t i = i0; i < i1; ++i) {
+        const int64_t bi = i >> shift;
+        dv.each(i, [&](int32_t j) {
+          ++tot;
+          in += (int64_t(j) >> shift) == bi;
+        });
+      }
+      internal[t] = in;
+      total[t] = tot;
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+    int64_t in = 0, tot = 0;
+    for (int t = 0; t < T; ++t) in += internal[t], tot += total[t];
+    mode = (tot > 0 && 2 * in >= tot) ? 1 : 0;
+  }
+  if (const char *e = getenv("MPK_TRSV_MODE")) mode = (e[0] == 'b') ? 1 : (e[0] == 'l' ? 0 : mode);
+  if (blk_rows <= 0) mode = 0;  // blocked schedule not available
+  return mode;
+}
+
 void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
                        HostPlan &p) {
+  // p.mode was set by plan_mode.  Global levels are needed by the level
+  // schedule and, for the L sweep, by the factorisation; a blocked sweep
+  // of U, U^H or L^H needs none.
+  if (p.mode == 1 && kind != 0) {
+    p.nlev = 0;
+    return;
+  }
   const int64_t n = h.n;
   const HostCsr &g = (kind >= 2) ? *ht : h;
   const DepView dv{g.rp, g.ci, kind == 0 || kind == 2};
   const bool forward = (kind == 0 || kind == 2);
-  int shift = 0;
-  while ((int64_t(1) << shift) < blk_rows) ++shift;
-  // global levels (the level schedule and the factorisation need them), and
-  // the share of block-internal dependencies that picks the schedule
   std::vector<int32_t> lvl(size_t(n), 0);
   int32_t nlev = n > 0 ? 1 : 0;
-  int64_t internal = 0, total = 0;
   for (int64_t t = 0; t < n; ++t) {
     const int64_t i = forward ? t : n - 1 - t;
-    const int64_t bi = i >> shift;
     int32_t l = 0;
-    dv.each(i, [&](int32_t j) {
-      l = std::max(l, lvl[j] + 1);
-      ++total;
-      internal += (int64_t(j) >> shift) == bi;
-    });
+    dv.each(i, [&](int32_t j) { l = std::max(l, lvl[j] + 1); });
     lvl[i] = l;
     nlev = std::max(nlev, l + 1);
   }
-  p.mode = (total > 0 && 2 * internal >= total) ? 1 : 0;
-  if (const char *e = getenv("MPK_TRSV_MODE")) p.mode = (e[0] == 'b') ? 1 : (e[0] == 'l' ? 0 : p.mode);
-  if (blk_rows <= 0) p.mode = 0;  // blocked schedule not available
+  (void)blk_rows;
   p.nlev = nlev;
   auto counting_order = [&](std::vector<int32_t> &levptr, std::vector<int32_t> &order) {
     levptr.assign(size_t(nlev) + 1, 0);
@@ -433,6 +468,7 @@ void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_ro
 }
 
 void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p) {
+  p.mode = plan_mode(h, ht, kind, blk_rows);
   build_plan_levels(h, ht, kind, blk_rows, p);
   build_plan_blocks(h, ht, kind, blk_rows, p);
 }

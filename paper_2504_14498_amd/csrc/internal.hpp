@@ -174,7 +174,10 @@ int ilu0_apply_launch(const Ilu0 &M, int K, int conj, const double *r, double *z
                       int32_t *abort_reset, int32_t *abort_flag, const int32_t *done,
                       hipStream_t s);
 int spmv_launch(int C, int K, int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
-                const double *x, double *y, const int32_t *done, hipStream_t s);
+                const double *x, double *y, const int32_t *done, hipStream_t s,
+                int lanes = 1);
+// Lanes per row of the standalone SpMV chosen for A (1 unless set or tuned).
+int spmv_lanes(const mpk_csr *A);
 int validate_csr_args(const mpk_csr *A);
 int csr_check_device_values(const mpk_csr *A, int C, int32_t *word, int64_t *bad_row,
                             hipStream_t s);
@@ -258,9 +261,12 @@ struct HostPlan {
 // 3 = L^H (columns of the strict lower part, backward).
 // ht: the transposed pattern (needed for kinds 2 and 3 only).
 void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, HostPlan &p);
-// The two halves of build_plan: global levels, the schedule choice, the
-// factorisation order (kind 0) and the level schedule; then the blocked
-// schedule when it was chosen.
+// The parts of build_plan: the schedule choice (plan_mode, whose result
+// goes to p.mode first); global levels where needed (the factorisation
+// order of kind 0, the level schedule); the blocked schedule when it was
+// chosen.  With p.mode set, the last two touch different fields of p and
+// may run on different threads.
+int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows);
 void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
                        HostPlan &p);
 void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,

@@ -125,6 +125,50 @@ __device__ __forceinline__ el<C, K> row_spmv(int64_t i, const int32_t *__restric
   return acc;
 }
 
+// Vector-CSR SpMV: G lanes per row (G = 2, 4, 8, 16).  Lane s of a row's
+// group loads and multiplies entries a + s, a + s + G, ... (so the group's
+// loads of indices and values are contiguous and the gathers of x are
+// spread evenly over its lanes); the group then adds the products in
+// ascending column order, every lane taking them from their lanes, so all
+// lanes of the group end with the row's sum.  The products and the order
+// of the additions are row_spmv's, so y is the same bit for bit.  Launch
+// with xcd_grid(ceil(n / (BLOCK / G))) workgroups.
+template <int C, int K, int G>
+__global__ __launch_bounds__(BLOCK) void spmv_vec(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ val,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y, const int32_t *done) {
+  static_assert(G >= 2 && G <= 16 && (G & (G - 1)) == 0, "lanes per row");
+  if (done && *done) return;
+  constexpr int RPB = BLOCK / G;  // rows per workgroup
+  const int64_t lb = xcd_block();
+  if (lb * RPB >= n) return;
+  const int64_t i = lb * RPB + threadIdx.x / G;
+  const int s = int(threadIdx.x % G);
+  const int g0 = int(threadIdx.x % WAVE) - s;  // the group's first lane in the wavefront
+  const bool valid = i < n;
+  const int32_t a = valid ? rp[i] : 0, b = valid ? rp[i + 1] : 0;
+  el<C, K> acc = el_zero<C, K>();
+  for (int32_t q0 = a; q0 < b; q0 += G) {
+    const int32_t q = q0 + s < b ? q0 + s : a;  // a lane past the row's end redoes entry a
+    double f[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) f[c] = val[size_t(q) * C + c];
+    const el<C, K> t = el_mul_f<C, K, 1>(f, el_load<C, K>(x + size_t(ci[q]) * C * K));
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      el<C, K> tu;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) tu.c[c].v[kk] = __shfl(t.c[c].v[kk], g0 + u, WAVE);
+      if (q0 + u < b) acc = q0 + u == a ? tu : el_add<C, K>(acc, tu);
+    }
+  }
+  if (valid && s == 0) el_store<C, K>(y + size_t(i) * C * K, acc);
+}
+
 // Generic row/element kernel: op(i, dots) for i < n; optional ND fused
 // inner-product partials written per row block.  Skipped when *done.
 // Launch with xcd_grid(nblocks(n)) workgroups.

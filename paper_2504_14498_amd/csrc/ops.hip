@@ -4,7 +4,9 @@
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <thread>
 
 #include "kernels.hpp"
@@ -40,14 +42,49 @@ int csr_check_device_values(const mpk_csr *A, int C, int32_t *word, int64_t *bad
 }
 
 int spmv_launch(int C, int K, int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
-                const double *x, double *y, const int32_t *done, hipStream_t s) {
+                const double *x, double *y, const int32_t *done, hipStream_t s, int lanes) {
   if (n == 0) return MPK_OK;
   return dispatch_ck(C, K, [&]<int CC, int KK>() {
-    SpmvOp<CC, KK> op{rp, ci, val, x, y};
-    hipLaunchKernelGGL((row_kernel<CC, KK, 0, SpmvOp<CC, KK>>), dim3(xcd_grid(nblocks(n))), dim3(BLOCK), 0,
-                       s, n, op, done, (double *)nullptr);
+    auto vec = [&]<int G>() {
+      const unsigned nb = unsigned((n + BLOCK / G - 1) / (BLOCK / G));
+      hipLaunchKernelGGL((spmv_vec<CC, KK, G>), dim3(xcd_grid(nb)), dim3(BLOCK), 0, s, n, rp, ci,
+                         val, x, y, done);
+    };
+    switch (lanes) {
+      case 2: vec.template operator()<2>(); break;
+      case 4: vec.template operator()<4>(); break;
+      case 8: vec.template operator()<8>(); break;
+      case 16: vec.template operator()<16>(); break;
+      default: {
+        SpmvOp<CC, KK> op{rp, ci, val, x, y};
+        hipLaunchKernelGGL((row_kernel<CC, KK, 0, SpmvOp<CC, KK>>), dim3(xcd_grid(nblocks(n))),
+                           dim3(BLOCK), 0, s, n, op, done, (double *)nullptr);
+      }
+    }
     return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
   });
+}
+
+// Lanes per row of the standalone SpMV, per matrix (its three device
+// arrays and n): set by mpk_spmv_set_lanes or mpk_spmv_tune; 1 (one lane
+// per row) otherwise.
+namespace {
+struct LanesKey {
+  const void *rp, *ci, *val;
+  int64_t n;
+  bool operator<(const LanesKey &o) const {
+    return std::tie(rp, ci, val, n) < std::tie(o.rp, o.ci, o.val, o.n);
+  }
+};
+std::mutex lanes_mu;
+std::map<LanesKey, int> lanes_table;
+LanesKey lanes_key(const mpk_csr *A) { return {A->row_ptr, A->col_idx, A->val, A->n}; }
+}  // namespace
+
+int spmv_lanes(const mpk_csr *A) {
+  std::lock_guard<std::mutex> lock(lanes_mu);
+  auto it = lanes_table.find(lanes_key(A));
+  return it == lanes_table.end() ? 1 : it->second;
 }
 
 // ------------------------------------------------------------- ILU(0)
@@ -212,7 +249,11 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     // (and adjoint) ones are built on other host threads.  The forward
     // sweep's global levels give the factorisation order, so the level-by-
     // level factorisation is launched as soon as they exist and runs on the
-    // device while the blocked schedules are built on the host.
+    // device while the blocked schedules are built on the host; the forward
+    // sweep's blocked schedule needs only the schedule choice and is built
+    // on its own thread meanwhile.
+    hp[0].mode = plan_mode(h, nullptr, 0, br);
+    std::thread t0([&] { build_plan_blocks(h, nullptr, 0, br, hp[0]); });
     std::thread t1([&] { build_plan(h, nullptr, 1, br, hp[1]); });
     std::thread t2;
     if (adj) {
@@ -241,7 +282,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     }
     if (!st)
       st = dispatch_ck(C, KF, [&]<int CC, int KK>() { return ilu0_levels<CC, KK>(*M, s); });
-    build_plan_blocks(h, nullptr, 0, br, hp[0]);
+    t0.join();
     t1.join();
     if (adj) t2.join();
     if (st) return st;
@@ -387,7 +428,9 @@ static int csr_spmv(int C, mpk_prec xp, const mpk_csr *A, int trans, const doubl
   if (st) return st;
   if (xp < MPK_D || xp > MPK_QD || !x || !y) return MPK_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (!trans) return spmv_launch(C, int(xp), A->n, A->row_ptr, A->col_idx, A->val, x, y, nullptr, s);
+  if (!trans)
+    return spmv_launch(C, int(xp), A->n, A->row_ptr, A->col_idx, A->val, x, y, nullptr, s,
+                       spmv_lanes(A));
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) ||
       ws_bytes < mpk_spmv_workspace_bytes(A, C == 2, 1))
     return MPK_EWORKSPACE;
@@ -528,6 +571,56 @@ int mpk_dot_noalloc(mpk_prec p, int is_complex, int64_t n, const double *a, cons
                        out);
     return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
   });
+}
+
+int mpk_spmv_set_lanes(const mpk_csr *A, int lanes) {
+  if (validate_csr_args(A)) return MPK_EINVAL;
+  if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
+    return MPK_EINVAL;
+  std::lock_guard<std::mutex> lock(lanes_mu);
+  if (lanes == 0)
+    lanes_table.erase(lanes_key(A));
+  else
+    lanes_table[lanes_key(A)] = lanes;
+  return MPK_OK;
+}
+
+int mpk_spmv_tune(mpk_prec xp, const mpk_csr *A, int is_complex, const double *x, double *y,
+                  int *lanes, double *ms, void *stream) {
+  if (validate_csr_args(A) || xp < MPK_D || xp > MPK_QD || !x || !y) return MPK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = is_complex ? 2 : 1;
+  const int cand[] = {1, 2, 4, 8, 16};
+  hipEvent_t e0, e1;
+  MPK_HIP(hipEventCreate(&e0));
+  MPK_HIP(hipEventCreate(&e1));
+  int best = 1, st = MPK_OK;
+  float best_ms = 0;
+  for (int k = 0; k < 5 && !st; ++k) {
+    const int g = cand[k];
+    float t = 0;
+    st = spmv_launch(C, int(xp), A->n, A->row_ptr, A->col_idx, A->val, x, y, nullptr, s, g);
+    if (!st && hipEventRecord(e0, s) != hipSuccess) st = MPK_EDEVICE;
+    for (int r = 0; r < 3 && !st; ++r)
+      st = spmv_launch(C, int(xp), A->n, A->row_ptr, A->col_idx, A->val, x, y, nullptr, s, g);
+    if (!st && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      st = MPK_EDEVICE;
+    if (!st && (k == 0 || t < best_ms)) {
+      best_ms = t;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> lock(lanes_mu);
+    lanes_table[lanes_key(A)] = best;
+  }
+  if (lanes) *lanes = best;
+  if (ms) *ms = best_ms / 3;
+  return MPK_OK;
 }
 
 }  // extern "C"

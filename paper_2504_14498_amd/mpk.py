@@ -84,6 +84,9 @@ SIGNATURES = [
     ("mpk_gnn_adam", _I, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, _P, _P, _P, _P, _P]),
     ("mpk_ilu0_correct", _I, [_P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
+    ("mpk_spmv_set_lanes", _I, [_CSRP, _I]),
+    ("mpk_spmv_tune", _I, [_I, _CSRP, _I, _P, _P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
+                           _P]),
     ("mpk_dot_workspace_bytes", _S, [_I64, _I, _I]),
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
     ("mpk_dot_noalloc_max_elements", _S, [_I, _I]),
@@ -181,6 +184,25 @@ def csr_spmv(A, x, y=None, trans=False, stream=None):
     _check(fn(K, ctypes.byref(A.c), int(trans), _ptr(x), _ptr(y), ctypes.c_void_p(ws_ptr), ws_n,
               _stream(stream)), "csr_spmv")
     return y
+
+
+def spmv_set_lanes(A, lanes):
+    """Lanes per row of A's SpMV (1, 2, 4, 8, 16; 0 = forget)."""
+    _check(_lib().mpk_spmv_set_lanes(ctypes.byref(A.c), int(lanes)), "spmv_set_lanes")
+
+
+def spmv_tune(A, x, y=None, stream=None):
+    """Time each lanes-per-row choice for A with vector x and keep the
+    fastest; returns (lanes, ms per launch)."""
+    n, C, K = x.shape
+    if y is None:
+        y = torch.empty_like(x)
+    lanes = ctypes.c_int(0)
+    ms = ctypes.c_double(0)
+    _check(_lib().mpk_spmv_tune(K, ctypes.byref(A.c), int(C == 2), _ptr(x), _ptr(y),
+                                ctypes.byref(lanes), ctypes.byref(ms), _stream(stream)),
+           "spmv_tune")
+    return lanes.value, ms.value
 
 
 class Ilu0:

@@ -77,6 +77,54 @@ def test_spmv_bitwise(mpk, orc, name, K):
     assert np.array_equal(y, yo)
 
 
+@pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv3d", "rdd"])
+@pytest.mark.parametrize("K", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+def test_spmv_vector_csr_bitwise(mpk, orc, name, K, lanes):
+    """Vector CSR (lanes per row > 1): the same products added in the same
+    order, so y equals the oracle's bit for bit."""
+    p = case(name)
+    A = mpk.Csr.from_problem(p)
+    mpk.spmv_set_lanes(A, lanes)
+    x = rand_vec(np.random.default_rng(K + lanes), p.n, p.C, K)
+    y = host(mpk.csr_spmv(A, dev(x)))
+    mpk.spmv_set_lanes(A, 0)
+    assert np.array_equal(y, orc.spmv(p.row_ptr, p.col_idx, p.val, x))
+
+
+@pytest.mark.parametrize("C,K", [(1, 2), (2, 3)])
+@pytest.mark.parametrize("lanes", [2, 4, 16])
+def test_spmv_vector_csr_ragged_rows_bitwise(mpk, orc, C, K, lanes):
+    """Empty rows, rows shorter and longer than a group, a last empty row."""
+    rng = np.random.default_rng(71 + K + lanes)
+    n = 1337
+    lens = rng.choice([0, 1, 2, 3, 15, 16, 17, 33, 70], size=n)
+    lens[-1] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n, size=l, replace=False)) for l in lens if l > 0]
+                        ).astype(np.int32)
+    val = rng.standard_normal((len(ci), C)) if C == 2 else rng.standard_normal(len(ci))
+    A = mpk.Csr(rp, ci, val)
+    mpk.spmv_set_lanes(A, lanes)
+    x = rand_vec(np.random.default_rng(K), n, C, K)
+    y = host(mpk.csr_spmv(A, dev(x)))
+    assert np.array_equal(y, orc.spmv(rp, ci, val, x))
+    assert np.all(y[lens == 0] == 0)
+
+
+def test_spmv_tune_keeps_results(mpk, orc):
+    """The tuner picks one of the choices and the SpMV then gives the same
+    bits as the oracle."""
+    p = case("rdd")
+    A = mpk.Csr.from_problem(p)
+    x = rand_vec(np.random.default_rng(3), p.n, p.C, 2)
+    lanes, ms = mpk.spmv_tune(A, dev(x))
+    assert lanes in (1, 2, 4, 8, 16) and ms > 0
+    y = host(mpk.csr_spmv(A, dev(x)))
+    mpk.spmv_set_lanes(A, 0)
+    assert np.array_equal(y, orc.spmv(p.row_ptr, p.col_idx, p.val, x))
+
+
 @pytest.mark.parametrize("C", [1, 2])
 @pytest.mark.parametrize("K", [1, 2, 3, 4])
 def test_spmv_ragged_rows_bitwise(mpk, orc, C, K):

@@ -61,6 +61,10 @@ def lib():
         L.or_krylov_with_factor.argtypes = [c_int, i64, _I32, _I32, _D, c_int, c_int, c_int, _D,
                                             _D, _D, dbl, dbl, i64, _I64, _D, _D, _I64, _D, i64]
         L.or_krylov_with_factor.restype = c_int
+        L.or_greedy_color.argtypes = [i64, _I32, _I32, _I32]
+        L.or_greedy_color.restype = i32
+        L.or_color_perm.argtypes = [i64, _I32, i32, _I32]
+        L.or_csr_permute.argtypes = [i64, _I32, _I32, _D, c_int, _I32, _I32, _I32, _D]
         _lib = L
     return _lib
 
@@ -276,3 +280,52 @@ def krylov(method, rp, ci, val, b, kf, tol_rel, tol_abs=0.0, max_iter=1000, x0=N
     return {"status": st, "x": x, "iters": iters.value, "relres_recursive": rr.value,
             "relres_true": rt.value, "bad_row": bad.value,
             "hist": hist[: min(hist_len, iters.value)]}
+
+
+# ------------------------------------------------- multicolour ordering
+# A labelled variant beyond the paper's method (its Section 5 leaves the
+# parallelisation of ILU(0) to future work): ILU(0) of P A P^T for an
+# ordering P by colours.
+
+
+def greedy_color(rp, ci):
+    """Greedy colouring of the graph of A + A^T in natural order (vertex i
+    takes the smallest colour absent from its neighbours j < i): returns
+    (color int32[n], number of colours)."""
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    n = len(rp) - 1
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    ncol = lib().or_greedy_color(n, _i32(rp), _i32(ci), _i32(color))
+    return color[:n], int(ncol)
+
+
+def color_perm(color, ncol):
+    """perm[k] = the row placed at position k: ascending colour, original
+    order within a colour."""
+    color = np.ascontiguousarray(color, dtype=np.int32)
+    n = len(color)
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    lib().or_color_perm(n, _i32(color), int(ncol), _i32(perm))
+    return perm[:n]
+
+
+def multicolor_perm(rp, ci):
+    """The multicolour ordering of A's pattern: (perm, number of colours)."""
+    color, ncol = greedy_color(rp, ci)
+    return color_perm(color, ncol), ncol
+
+
+def csr_permute(rp, ci, val, C, perm):
+    """B = P A P^T (b_kl = a_{perm[k], perm[l]}), columns ascending per row:
+    (brp, bci, bval[nnz, C])."""
+    rp, ci, val = _csr(rp, ci, val, C)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    n = len(rp) - 1
+    nnz = int(rp[-1])
+    brp = np.zeros(n + 1, dtype=np.int32)
+    bci = np.zeros(max(nnz, 1), dtype=np.int32)
+    bval = np.zeros((max(nnz, 1), C))
+    lib().or_csr_permute(n, _i32(rp), _i32(ci), _d(val), C, _i32(perm), _i32(brp), _i32(bci),
+                         _d(bval))
+    return brp, bci[:nnz], bval[:nnz]

@@ -1566,3 +1566,106 @@ int or_krylov_with_factor(int method, int64_t n, const int32_t *rp, const int32_
     return krylov_impl(method, n, rp, ci, val, C, K, kf, f, b, x, eps_r, eps_a, max_iter,
                        iters, relres_recursive, relres_true, bad_row, hist, hist_len);
 }
+
+/* ------------------------------------------------------------------ */
+/* Multicolour ordering: a labelled variant beyond the paper's method  */
+/* (Section 5 leaves parallelising the ILU(0) routines to future work). */
+/* The solve of P A P^T y = P b with ILU(0) of P A P^T is a different   */
+/* preconditioner from ILU(0) of A.                                     */
+/* ------------------------------------------------------------------ */
+
+/* Greedy colouring of the graph of A + A^T in natural order: vertices i
+ * != j are adjacent when a_ij or a_ji is stored, and vertex i = 0, 1, ...
+ * takes the smallest colour that no adjacent vertex j < i has.  Writes
+ * color[n]; returns the number of colours (0 when n = 0). */
+int32_t or_greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32_t *color)
+{
+    int64_t i, p, nnz = rp[n];
+    int32_t ncol = 0;
+    /* the pattern of A^T: rows j holding column i, listed under i */
+    int32_t *trp = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *tci = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 2));
+    for (p = 0; p < nnz; ++p)
+        trp[ci[p] + 1]++;
+    for (i = 0; i < n; ++i)
+        trp[i + 1] += trp[i];
+    for (i = 0; i < n; ++i)
+        fill[i] = trp[i];
+    for (i = 0; i < n; ++i)
+        for (p = rp[i]; p < rp[i + 1]; ++p)
+            tci[fill[ci[p]]++] = (int32_t)i;
+    /* seen[c] == i: colour c is taken by a neighbour of i numbered below i */
+    for (i = 0; i < n + 2; ++i)
+        seen[i] = -1;
+    for (i = 0; i < n; ++i) {
+        int32_t c = 0;
+        for (p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] < i)
+                seen[color[ci[p]]] = i;
+        for (p = trp[i]; p < trp[i + 1]; ++p)
+            if (tci[p] < i)
+                seen[color[tci[p]]] = i;
+        while (seen[c] == i)
+            ++c;
+        color[i] = c;
+        if (c + 1 > ncol)
+            ncol = c + 1;
+    }
+    free(trp);
+    free(tci);
+    free(fill);
+    free(seen);
+    return ncol;
+}
+
+/* The ordering by colour: perm[k] is the row of A placed at position k;
+ * rows are grouped by colour in ascending colour, and keep their order
+ * within a colour. */
+void or_color_perm(int64_t n, const int32_t *color, int32_t ncol, int32_t *perm)
+{
+    int64_t i;
+    int32_t c, k = 0;
+    for (c = 0; c < ncol; ++c)
+        for (i = 0; i < n; ++i)
+            if (color[i] == c)
+                perm[k++] = (int32_t)i;
+}
+
+/* B = P A P^T for the permutation perm (perm[k] = the row of A placed at
+ * k): b_kl = a_{perm[k], perm[l]}, stored with each row's columns in
+ * ascending order.  brp[n+1], bci[nnz], bval[nnz*C]. */
+void or_csr_permute(int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                    int C, const int32_t *perm, int32_t *brp, int32_t *bci, double *bval)
+{
+    int64_t k, p, q;
+    int v;
+    int32_t *iperm = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    for (k = 0; k < n; ++k)
+        iperm[perm[k]] = (int32_t)k;
+    brp[0] = 0;
+    for (k = 0; k < n; ++k)
+        brp[k + 1] = brp[k] + (rp[perm[k] + 1] - rp[perm[k]]);
+    for (k = 0; k < n; ++k) {
+        int64_t a = rp[perm[k]], len = rp[perm[k] + 1] - a, o = brp[k];
+        /* row perm[k] with its columns renamed, then sorted by insertion */
+        for (p = 0; p < len; ++p) {
+            int32_t col = iperm[ci[a + p]];
+            double w[2];
+            for (v = 0; v < C; ++v)
+                w[v] = val[(a + p) * C + v];
+            q = p;
+            while (q > 0 && bci[o + q - 1] > col) {
+                bci[o + q] = bci[o + q - 1];
+                for (v = 0; v < C; ++v)
+                    bval[(o + q) * C + v] = bval[(o + q - 1) * C + v];
+                --q;
+            }
+            bci[o + q] = col;
+            for (v = 0; v < C; ++v)
+                bval[(o + q) * C + v] = w[v];
+        }
+    }
+    free(iperm);
+}

@@ -121,6 +121,47 @@ int mpk_spmv_set_lanes(const mpk_csr *A, int lanes);
 int mpk_spmv_tune(mpk_prec xp, const mpk_csr *A, int is_complex, const double *x, double *y,
                   int *lanes, double *ms, void *stream);
 
+/* ------------------------------------------------- multicolour ordering
+ * A labelled variant beyond the paper's method: Section 5 leaves the
+ * parallelisation of the ILU(0) routines to future work.  The rows are
+ * coloured and ordered by colour, B = P A P^T is formed, and B y = P b is
+ * solved with ILU(0) of B; x = P^T y.  ILU(0) of B is a different
+ * preconditioner from ILU(0) of A (usually more passes), but in B a row of
+ * colour c has stored lower entries only in columns of colours below c,
+ * so each substitution runs at most one level per colour, each a set of
+ * independent rows.
+ *
+ * mpk_multicolor_order: the greedy colouring of the graph of A + A^T in
+ * natural order (rows i != j are adjacent when a_ij or a_ji is stored; row
+ * i = 0, 1, ... takes the smallest colour that no adjacent row j < i has)
+ * and the ordering by colour: perm[k] = the row of A placed at position k,
+ * colours ascending, rows in their original order within a colour.
+ * perm: device int32[n], written; *ncolors (host) receives the number of
+ * colours.  The pattern is checked as for ILU(0) (MPK_EPATTERN,
+ * MPK_ENO_DIAG).  The colouring runs on the host (the pattern is copied
+ * there).  Synchronous. */
+int mpk_multicolor_order(const mpk_csr *A, int32_t *perm, int32_t *ncolors, void *stream);
+/* B = P A P^T for a permutation perm (device int32[n], perm[k] = the row
+ * of A placed at k): b_kl = a_{perm[k], perm[l]}, each row's columns in
+ * ascending order, values copied exactly.  b_row_ptr[n+1], b_col_idx[nnz]
+ * and b_val[nnz*C] are device arrays of the caller, written here (B has
+ * A's n and nnz).  ws: mpk_csr_permute_workspace_bytes(n) bytes of device
+ * memory, 256-byte aligned (MPK_EWORKSPACE otherwise).  MPK_EINVAL when
+ * perm does not hold every row exactly once; MPK_EPATTERN when A's
+ * row_ptr or col_idx are out of range.  Synchronous. */
+size_t mpk_csr_permute_workspace_bytes(int64_t n);
+int mpk_dcsr_permute(const mpk_csr *A, const int32_t *perm, int32_t *b_row_ptr,
+                     int32_t *b_col_idx, double *b_val, void *ws, size_t ws_bytes, void *stream);
+int mpk_zcsr_permute(const mpk_csr *A, const int32_t *perm, int32_t *b_row_ptr,
+                     int32_t *b_col_idx, double *b_val, void *ws, size_t ws_bytes, void *stream);
+/* y = P x (inverse = 0: y[k] = x[perm[k]]) or y = P^T x (inverse = 1:
+ * y[perm[k]] = x[k]) for device vectors of n elements of (is_complex ? 2 :
+ * 1) * vp doubles.  perm should be a permutation (mpk_?csr_permute checks
+ * one); an entry outside [0, n) is skipped, nothing is read or written
+ * for it.  x and y must not overlap.  Asynchronous on stream. */
+int mpk_vec_permute(mpk_prec vp, int is_complex, int64_t n, const int32_t *perm, int inverse,
+                    const double *x, double *y, void *stream);
+
 /* --------------------------------------------------------------- ILU(0)
  * ILU(0) factorisation (Algorithm 1) on the stored pattern of A, in factor
  * precision fp = MPK_D (binary64: the "_d_ILU(0)" factor of Section 4) or

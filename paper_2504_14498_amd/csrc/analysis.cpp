@@ -134,6 +134,79 @@ void host_transpose(const HostCsr &h, IVec &trp, IVec &tci, IVec &tsrc) {
     }
 }
 
+// Greedy colouring of the graph of A + A^T in natural order: rows i != j
+// are adjacent when a_ij or a_ji is stored, and row i = 0, 1, ... takes
+// the smallest colour that no adjacent row j < i has.  Its neighbours
+// below i come from the lower part of row i and from the rows j < i that
+// store column i (the lower part of row i of A^T).  Returns the number of
+// colours.
+int32_t greedy_color(const HostCsr &h, IVec &color) {
+  const int64_t n = h.n, nnz = h.nnz;
+  // A structurally symmetric pattern (every stored a_ij has a stored a_ji,
+  // checked on up to 8 host threads) needs only its lower part: row i's
+  // neighbours below i are its columns below i.
+  bool sym = true;
+  {
+    const int T = int(std::min<int64_t>(8, std::max<int64_t>(1, n / 65536)));
+    std::vector<char> ok(size_t(T), 1);
+    auto work = [&](int t) {
+      const int64_t i0 = n * t / T, i1 = n * (t + 1) / T;
+      for (int64_t i = i0; i < i1 && ok[t]; ++i)
+        for (int32_t p = h.rp[i + 1] - 1; p >= h.rp[i] && h.ci[p] > i; --p) {
+          const int32_t j = h.ci[p];
+          if (!std::binary_search(h.ci + h.rp[j], h.ci + h.rp[j + 1], int32_t(i))) {
+            ok[t] = 0;
+            break;
+          }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+    for (int t = 0; t < T; ++t) sym = sym && ok[t];
+  }
+  // otherwise the lower part of A^T as well: row c lists the rows j < c
+  // that store column c (their upper entries), ascending j
+  IVec trp(size_t(n) + 1, 0), tci(size_t(std::max<int64_t>(sym ? 1 : nnz, 1)));
+  if (!sym) {
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t p = h.rp[j + 1] - 1; p >= h.rp[j] && h.ci[p] > j; --p) trp[h.ci[p] + 1]++;
+    for (int64_t i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    IVec next(trp.begin(), trp.end() - 1);
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t p = h.rp[j]; p < h.rp[j + 1]; ++p)
+        if (h.ci[p] > j) tci[next[h.ci[p]]++] = int32_t(j);
+  }
+  color.resize(size_t(n));  // each entry is written before it is read
+  // the colours of row i's neighbours below i: a bit mask while they are
+  // below 64, else seen[c] == i marks colour c as taken
+  IVec seen;
+  int32_t ncol = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t mask = 0;
+    auto take = [&](int32_t c) {
+      if (c < 64) mask |= uint64_t(1) << c;
+    };
+    for (int32_t p = h.rp[i]; p < h.rp[i + 1] && h.ci[p] < i; ++p) take(color[h.ci[p]]);
+    for (int32_t p = trp[i]; p < trp[i + 1]; ++p) take(color[tci[p]]);
+    int32_t c;
+    if (~mask != 0) {
+      c = __builtin_ctzll(~mask);  // smallest colour not taken (below 64)
+    } else {
+      if (seen.empty()) seen.assign(size_t(n) + 2, -1);
+      const int32_t me = int32_t(i);
+      for (int32_t p = h.rp[i]; p < h.rp[i + 1] && h.ci[p] < i; ++p) seen[color[h.ci[p]]] = me;
+      for (int32_t p = trp[i]; p < trp[i + 1]; ++p) seen[color[tci[p]]] = me;
+      c = 64;
+      while (seen[c] == me) ++c;
+    }
+    color[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  return ncol;
+}
+
 // Rows per block of the blocked schedule: the block's results live in LDS,
 // at most 128 KiB for quad-double (K = 4).
 int default_block_rows(int C, int kmax) {
@@ -219,8 +292,9 @@ static BlockGeom deep_geom(const DepView &dv, int64_t n, int cap) {
 
 // Schedule of a sweep: blocked (mode 1) when at least half of the
 // dependencies stay inside blocks of blk_rows consecutive rows, else the
-// level schedule (mode 0).  One pass over the pattern on up to 8 host
-// threads.
+// level schedule (mode 0, which build_plan_levels turns into mode 2, one
+// launch per level, when the levels are few and wide).  One pass over the
+// pattern on up to 8 host threads.
 int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows) {
   int mode = 0;
   if (blk_rows > 0) {
@@ -252,7 +326,10 @@ int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows) {
     for (int t = 0; t < T; ++t) in += internal[t], tot += total[t];
     mode = (tot > 0 && 2 * in >= tot) ? 1 : 0;
   }
-  if (const char *e = getenv("MPK_TRSV_MODE")) mode = (e[0] == 'b') ? 1 : (e[0] == 'l' ? 0 : mode);
+  // MPK_TRSV_MODE: b = blocked, l = polling level schedule, s = one launch
+  // per level (both level schedules start as mode 0 here)
+  if (const char *e = getenv("MPK_TRSV_MODE"))
+    mode = (e[0] == 'b') ? 1 : ((e[0] == 'l' || e[0] == 's') ? 0 : mode);
   if (blk_rows <= 0) mode = 0;  // blocked schedule not available
   return mode;
 }
@@ -291,6 +368,13 @@ void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_ro
   };
   if (kind == 0) counting_order(p.glob_levptr, p.glob_order);
   if (p.mode == 0) {
+    // few, wide levels (at least 16384 rows each on average, at most 64):
+    // one launch per level (mode 2) instead of one polling launch
+    const char *e = getenv("MPK_TRSV_MODE");
+    const bool force = e && e[0] == 's', forbid = e && e[0] == 'l';
+    if (force || (!forbid && nlev <= 64 && n >= int64_t(nlev) * 16384)) p.mode = 2;
+  }
+  if (p.mode != 1) {
     counting_order(p.levptr, p.order);
     p.seg.clear();
     p.seg_level.clear();

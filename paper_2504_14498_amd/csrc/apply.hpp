@@ -14,6 +14,17 @@ namespace mpk {
 template <int C, int K, int KF, bool DIV, bool CONJ>
 inline void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *abort_flag,
                         const int32_t *done, hipStream_t s) {
+  if (P.mode == 2) {
+    // one launch per level, in order
+    for (int32_t l = 0; l < P.nlev; ++l) {
+      const int32_t a = P.h_levptr[l], cnt = P.h_levptr[l + 1] - a;
+      if (cnt <= 0) continue;
+      hipLaunchKernelGGL((trsv_level<C, K, KF, DIV, CONJ>), dim3((cnt + BLOCK - 1) / BLOCK),
+                         dim3(BLOCK), 0, s, a, cnt, P.order, P.ptr, P.col, P.val, P.dval, rhs,
+                         out, done);
+    }
+    return;
+  }
   if (P.mode == 1) {
     static const int64_t bcap = [] {
       const char *e = getenv("MPK_TRSV_BGRID");
@@ -61,7 +72,9 @@ inline int apply_ckf(const Ilu0 &M, int conj, const double *r, double *z, int32_
   // blocked sweeps poll only the rows other blocks read; level sweeps poll
   // every row
   const int32_t *l1 = P1.mode == 1 ? P1.xlist : nullptr, *l2 = P2.mode == 1 ? P2.xlist : nullptr;
-  const int64_t c1 = P1.mode == 1 ? P1.nx : M.n, c2 = P2.mode == 1 ? P2.nx : M.n;
+  // level-synchronous sweeps (mode 2) poll nothing
+  const int64_t c1 = P1.mode == 1 ? P1.nx : (P1.mode == 2 ? 0 : M.n),
+                c2 = P2.mode == 1 ? P2.nx : (P2.mode == 2 ? 0 : M.n);
   const int64_t cover = std::max<int64_t>(std::max(c1, c2) * C * K, std::max(P1.nlev, P2.nlev));
   hipLaunchKernelGGL(trsv_prep, dim3(nblocks(std::max<int64_t>(cover, 1))), dim3(BLOCK), 0, s,
                      C * K, l1, c1, M.tmp, l2, c2, z, P1.nlev, P1.lev_done, P2.nlev, P2.lev_done,

@@ -112,7 +112,7 @@ struct Plan {
   int32_t *sync = nullptr;     // [0] ticket, [1] watchdog abort
   // blocked schedule (mode 1): contiguous row blocks in processing order,
   // each with its own local levels; positions are block-major
-  int32_t mode = 0;            // 0 level schedule, 1 blocked schedule
+  int32_t mode = 0;            // 0 level schedule, 1 blocked schedule, 2 one launch per level
   int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
   int32_t kmax = 4;            // largest vector precision the blocks are sized for
   int32_t blk_rows = 0;        // LDS slots per block (t * w)
@@ -277,5 +277,10 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s);
 
 // Transposed pattern with source map (for A^T / A^H products).
 void host_transpose(const HostCsr &h, IVec &trp, IVec &tci, IVec &tsrc);
+
+// Greedy colouring of the graph of A + A^T in natural order (row i takes
+// the smallest colour no adjacent row j < i has); returns the number of
+// colours.
+int32_t greedy_color(const HostCsr &h, IVec &color);
 
 }  // namespace mpk

@@ -610,6 +610,47 @@ __global__ __launch_bounds__(BLOCK) void trsv_syncfree(
   }
 }
 
+// Level-synchronous sweep: one launch per level, one thread per row of
+// the level (positions pos0 .. pos0 + cnt - 1 of the level order).  Rows of
+// one level depend only on rows of earlier levels, which earlier launches
+// on the same stream have finished, so nothing is polled and the loads are
+// plain cached loads.  For schedules with few, wide levels (a multicolour
+// ordering has one level per colour).  Row arithmetic is the level
+// schedule's: right-hand side, then each product subtracted in ascending
+// column order, then the division by the pivot (DIV).
+template <int C, int K, int KF, bool DIV, bool CONJ>
+__global__ __launch_bounds__(BLOCK) void trsv_level(
+    int32_t pos0, int32_t cnt, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ dval,
+    const double *__restrict__ rhs, double *__restrict__ out, const int32_t *done) {
+  if (done && *done) return;
+  constexpr int E = C * K;
+  const int32_t t = int32_t(blockIdx.x) * BLOCK + int32_t(threadIdx.x);
+  if (t >= cnt) return;
+  const int32_t pos = pos0 + t;
+  const int32_t i = order[pos];
+  const int32_t pb = ptr[pos], pe = ptr[pos + 1];
+  el<C, K> acc = el_load<C, K>(rhs + size_t(i) * E);
+  for (int32_t q = pb; q < pe; ++q) {
+    double f[C * KF];
+    load_f<C, KF, CONJ>(val + size_t(q) * C * KF, f);
+    acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, el_load<C, K>(out + size_t(col[q]) * E)));
+  }
+  if constexpr (DIV) {
+    double d[C * KF];
+    load_f<C, KF, CONJ>(dval + size_t(pos) * C * KF, d);
+    acc = el_div_k<C, K, KF>(acc, d);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = acc.c[c].v[k];
+      out[size_t(i) * E + c * K + k] = v != v ? __builtin_nan("") : v;
+    }
+}
+
 // Blocked schedule: a workgroup takes the next block of rows
 // (tickets hand blocks out in the sweep's order, so a block only waits on
 // blocks already taken by running workgroups) and walks the block's local

@@ -91,6 +91,11 @@ SIGNATURES = [
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
     ("mpk_dot_noalloc_max_elements", _S, [_I, _I]),
     ("mpk_dot_noalloc", _I, [_I, _I, _I64, _P, _P, _P, _P]),
+    ("mpk_multicolor_order", _I, [_CSRP, _P, ctypes.POINTER(ctypes.c_int32), _P]),
+    ("mpk_csr_permute_workspace_bytes", _S, [_I64]),
+    ("mpk_dcsr_permute", _I, [_CSRP, _P, _P, _P, _P, _P, _S, _P]),
+    ("mpk_zcsr_permute", _I, [_CSRP, _P, _P, _P, _P, _P, _S, _P]),
+    ("mpk_vec_permute", _I, [_I, _I, _I64, _P, _I, _P, _P, _P]),
 ]
 
 
@@ -143,9 +148,13 @@ class Csr:
     real or (nnz, 2) complex."""
 
     def __init__(self, row_ptr, col_idx, val, device="cuda"):
-        self.row_ptr = torch.as_tensor(np.asarray(row_ptr), dtype=torch.int32).to(device)
-        self.col_idx = torch.as_tensor(np.asarray(col_idx), dtype=torch.int32).to(device)
-        v = torch.as_tensor(np.asarray(val), dtype=torch.float64).to(device)
+        def dev(a, dtype):
+            if not isinstance(a, torch.Tensor):
+                a = torch.as_tensor(np.asarray(a))
+            return a.to(device=device, dtype=dtype).contiguous()
+        self.row_ptr = dev(row_ptr, torch.int32)
+        self.col_idx = dev(col_idx, torch.int32)
+        v = dev(val, torch.float64)
         self.is_complex = v.dim() == 2
         self.val = v.contiguous()
         self.n = self.row_ptr.numel() - 1
@@ -331,6 +340,59 @@ def krylov_solve(method, A, b, x0=None, fprec=1, tol_rel=1e-25, tol_abs=0.0, max
            "hist": hist[: min(hist_len, info.iters)] if hist_len else None,
            "workspace": workspace}
     return x, out
+
+
+def multicolor_order(A, stream=None):
+    """Greedy colouring of A + A^T in natural order and the ordering by
+    colour (a variant beyond the paper's method): returns (perm, number of
+    colours), perm an int32 CUDA tensor with perm[k] = the row placed at k."""
+    perm = torch.empty(A.n, dtype=torch.int32, device=A.device)
+    ncol = ctypes.c_int32(0)
+    _check(_lib().mpk_multicolor_order(ctypes.byref(A.c), _ptr(perm), ctypes.byref(ncol),
+                                       _stream(stream)), "multicolor_order")
+    return perm, ncol.value
+
+
+def csr_permute(A, perm, stream=None):
+    """B = P A P^T (b_kl = a_{perm[k], perm[l]}) as a new Csr."""
+    rp = torch.empty(A.n + 1, dtype=torch.int32, device=A.device)
+    ci = torch.empty(A.nnz, dtype=torch.int32, device=A.device)
+    val = torch.empty_like(A.val)
+    ws, ws_ptr, ws_n = _workspace(_lib().mpk_csr_permute_workspace_bytes(A.n), A.device)
+    fn = _lib().mpk_zcsr_permute if A.is_complex else _lib().mpk_dcsr_permute
+    _check(fn(ctypes.byref(A.c), _ptr(perm), _ptr(rp), _ptr(ci), _ptr(val),
+              ctypes.c_void_p(ws_ptr), ws_n, _stream(stream)), "csr_permute")
+    return Csr(rp, ci, val, A.device)
+
+
+def vec_permute(x, perm, inverse=False, out=None, stream=None):
+    """y = P x (y[k] = x[perm[k]]) or, inverse, y = P^T x (y[perm[k]] = x[k])."""
+    if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 3 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 CUDA tensor of shape (n, C, K)")
+    n, C, K = x.shape
+    y = torch.empty_like(x) if out is None else out
+    _check(_lib().mpk_vec_permute(K, int(C == 2), n, _ptr(perm), int(bool(inverse)), _ptr(x),
+                                  _ptr(y), _stream(stream)), "vec_permute")
+    return y
+
+
+def krylov_solve_multicolor(method, A, b, fprec=1, tol_rel=1e-25, tol_abs=0.0, max_iter=1000,
+                            hist_len=0, workspace=None, graph=True):
+    """The multicolour variant: order A by colours, solve P A P^T y = P b
+    with ILU(0) of P A P^T, return x = P^T y.  Calls, in order,
+    multicolor_order, csr_permute, vec_permute, krylov_solve and
+    vec_permute; info gains "ncolors"."""
+    cur = torch.cuda.current_stream(A.device)
+    perm, ncol = multicolor_order(A, stream=cur)
+    B = csr_permute(A, perm, stream=cur)
+    bp = vec_permute(b, perm, stream=cur)
+    y, info = krylov_solve(method, B, bp, fprec=fprec, tol_rel=tol_rel, tol_abs=tol_abs,
+                           max_iter=max_iter, hist_len=hist_len, workspace=workspace, graph=graph)
+    x = vec_permute(y, perm, inverse=True, stream=cur)
+    info["ncolors"] = ncol
+    info["perm"] = perm
+    info["B"] = B
+    return x, info
 
 
 def krylov_solve_batched(mats, bs, x0s=None, method="bicgstab", fprec=1, tol_rel=1e-25,

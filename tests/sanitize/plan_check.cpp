@@ -6,8 +6,13 @@
 // tridiagonal matrix and single-row and empty-dependency cases.  For every
 // plan it checks that the rows form a permutation and that every
 // dependency of a row is scheduled before the piece of work holding it.
+// The greedy colouring of the multicolour ordering is checked on the same
+// patterns: no two adjacent rows share a colour, and every colour below a
+// row's own is taken by a neighbour numbered before it.
 // Prints "ok" and exits 0 when all hold.
+#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <random>
 #include <vector>
 
@@ -79,7 +84,7 @@ HostCsr view(const Pattern &p) {
 }
 
 int fails = 0;
-int plans_of_mode[2] = {0, 0};
+int plans_of_mode[3] = {0, 0, 0};
 #define EXPECT(c)                                                                \
   do {                                                                           \
     if (!(c)) {                                                                  \
@@ -110,7 +115,7 @@ void check_plan(const HostCsr &h, const HostCsr &t, int kind, const HostPlan &p)
   // start position of the unit of work holding each position: a level
   // segment (level schedule) or a local-level piece (blocked schedule)
   std::vector<int32_t> start(size_t(n), 0);
-  if (p.mode == 0) {
+  if (p.mode != 1) {
     EXPECT(p.levptr.size() == size_t(p.nlev) + 1 && p.levptr[p.nlev] == n);
     for (int32_t l = 0; l < p.nlev; ++l)
       for (int32_t q = p.levptr[l]; q < p.levptr[l + 1]; ++q) start[q] = p.levptr[l];
@@ -140,6 +145,27 @@ void check_plan(const HostCsr &h, const HostCsr &t, int kind, const HostPlan &p)
     });
 }
 
+void check_color(const HostCsr &h, const HostCsr &t) {
+  IVec color;
+  const int32_t ncol = greedy_color(h, color);
+  int32_t top = -1;
+  for (int64_t i = 0; i < h.n; ++i) top = std::max(top, color[i]);
+  EXPECT(ncol == top + 1);
+  std::vector<char> taken;
+  for (int64_t i = 0; i < h.n; ++i) {
+    taken.assign(size_t(color[i]) + 1, 0);
+    // neighbours in A + A^T: the columns of row i of A and of A^T
+    for (const HostCsr *g : {&h, &t})
+      for (int32_t q = g->rp[i]; q < g->rp[i + 1]; ++q) {
+        const int32_t j = g->ci[q];
+        if (j == i) continue;
+        EXPECT(color[j] != color[i]);
+        if (j < i && color[j] < color[i]) taken[color[j]] = 1;
+      }
+    for (int32_t c = 0; c < color[i]; ++c) EXPECT(taken[c]);
+  }
+}
+
 void run(const Pattern &pat, const char *name) {
   const HostCsr h = view(pat);
   int64_t bad = -2;
@@ -157,11 +183,22 @@ void run(const Pattern &pat, const char *name) {
   t.ci = tci.data();
   for (int64_t p = 0; p < h.nnz; ++p)
     if (tsrc[p] < 0 || tsrc[p] >= h.nnz) ++fails;
+  check_color(h, t);
+  // the one-launch-per-level schedule, forced
+  setenv("MPK_TRSV_MODE", "s", 1);
+  for (int kind = 0; kind < 4; ++kind) {
+    HostPlan hp;
+    build_plan(h, &t, kind, 1024, hp);
+    EXPECT(hp.mode == 2);
+    plans_of_mode[hp.mode]++;
+    check_plan(h, t, kind, hp);
+  }
+  unsetenv("MPK_TRSV_MODE");
   for (int rows : {0, 64, 256, 1024, 8192})
     for (int kind = 0; kind < 4; ++kind) {
       HostPlan hp;
       build_plan(h, &t, kind, rows, hp);
-      plans_of_mode[hp.mode == 1]++;
+      plans_of_mode[hp.mode]++;
       check_plan(h, t, kind, hp);
     }
 }
@@ -195,7 +232,7 @@ int main() {
   run(random_pattern(700, 30, 6), "random 700");
   bad_patterns();
   // both schedules were built and checked
-  if (plans_of_mode[0] == 0 || plans_of_mode[1] == 0) ++fails;
+  if (plans_of_mode[0] == 0 || plans_of_mode[1] == 0 || plans_of_mode[2] == 0) ++fails;
   if (fails) {
     std::printf("%d failures\n", fails);
     return 1;

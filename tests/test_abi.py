@@ -138,3 +138,29 @@ def test_noalloc_dot_limits(lib):
                                ctypes.c_void_p(8), None) == -1
     assert lib.mpk_dot_noalloc(2, 0, 10, None, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                None) == -1
+
+
+def test_ordering_arguments_rejected_before_device_work(lib):
+    import ctypes as C
+    n32 = C.c_int32(0)
+    assert lib.mpk_multicolor_order(None, C.c_void_p(8), C.byref(n32), None) == -1
+    A = _csr(4, 4)
+    assert lib.mpk_multicolor_order(C.byref(A), None, C.byref(n32), None) == -1
+    assert lib.mpk_multicolor_order(C.byref(A), C.c_void_p(8), None, None) == -1
+    assert lib.mpk_csr_permute_workspace_bytes(0) == 0
+    assert lib.mpk_csr_permute_workspace_bytes(1000) >= 4000
+    for fn in (lib.mpk_dcsr_permute, lib.mpk_zcsr_permute):
+        assert fn(None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                  C.c_void_p(256), 1 << 20, None) == -1
+        assert fn(C.byref(A), None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                  C.c_void_p(256), 1 << 20, None) == -1
+        # missing, misaligned or short workspace
+        for ws, nb in ((None, 1 << 20), (C.c_void_p(264), 1 << 20), (C.c_void_p(256), 8)):
+            assert fn(C.byref(A), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                      ws, nb, None) == -3
+    # precision out of range, negative n, null arrays; n = 0 does nothing
+    assert lib.mpk_vec_permute(0, 0, 4, C.c_void_p(8), 0, C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.mpk_vec_permute(5, 0, 4, C.c_void_p(8), 0, C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.mpk_vec_permute(2, 0, -1, C.c_void_p(8), 0, C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.mpk_vec_permute(2, 0, 4, None, 0, C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.mpk_vec_permute(2, 1, 0, None, 0, None, None, None) == 0

@@ -176,6 +176,24 @@ def test_ilu0_apply_bitwise(mpk, orc, name, kf, K):
     assert np.array_equal(zh, zho)
 
 
+@pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv2d_tail", "conv3d", "helm", "rdd"])
+@pytest.mark.parametrize("kf,K", [(1, 2), (2, 2), (1, 4), (4, 4)])
+def test_ilu0_apply_level_launches_bitwise(mpk, orc, monkeypatch, name, kf, K):
+    """The one-launch-per-level sweeps (chosen by themselves for few, wide
+    levels; forced here on every case) against the oracle, bit for bit."""
+    monkeypatch.setenv("MPK_TRSV_MODE", "s")
+    p = case(name)
+    A = mpk.Csr.from_problem(p)
+    M = mpk.ilu0_factor(A, kf, adjoint=True)
+    st, bad, f = orc.ilu0(p.row_ptr, p.col_idx, p.val, p.C, kf)
+    assert st == 0
+    r = rand_vec(np.random.default_rng(7 * K + kf), p.n, p.C, K)
+    assert np.array_equal(host(mpk.ilu0_apply(M, dev(r))), orc.ilu0_apply(p.row_ptr, p.col_idx,
+                                                                           f, r))
+    assert np.array_equal(host(mpk.ilu0_apply(M, dev(r), conj_trans=True)),
+                          orc.ilu0_apply(p.row_ptr, p.col_idx, f, r, conj_trans=True))
+
+
 def complex_grid2d(m, seed):
     """A complex matrix on the 5-point pattern of an m x m grid (diagonally
     dominant): the pattern of config1 with random complex values."""
@@ -344,6 +362,31 @@ def test_solve_parity_deep_blocks(mpk, orc, monkeypatch, method, K, kf):
     monkeypatch.setenv("MPK_TRSV_BLOCK_ROWS", "256")
     p = W.config2(20)
     tol = 1e-25 if K == 2 else 1e-35
+    b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K))
+    ref = orc.krylov(method, p.row_ptr, p.col_idx, p.val, b, kf=kf, tol_rel=tol, max_iter=3000,
+                     hist_len=3000)
+    assert ref["status"] == 0, ref["status"]
+    A = mpk.Csr.from_problem(p)
+    x, info = mpk.krylov_solve(method, A, dev(b), fprec=kf, tol_rel=tol, max_iter=3000,
+                               hist_len=3000)
+    assert info["status"] == "ok", info
+    rel = true_relres(orc, p, host(x), b)
+    assert rel <= tol * RES_MARGIN, (rel, tol)
+    assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
+    h, ho = host(info["hist"]), ref["hist"]
+    m = min(20, len(h), len(ho))
+    assert np.allclose(h[:m], ho[:m], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name,method,K,kf,tol", [("conv2d", "bicgstab", 2, 1, 1e-20),
+                                                  ("helm", "gpbicg", 2, 1, 1e-25),
+                                                  ("rdd", "bicg", 2, 1, 1e-25),
+                                                  ("conv3d", "cgs", 3, 3, 1e-30)])
+def test_solve_parity_level_launches(mpk, orc, monkeypatch, name, method, K, kf, tol):
+    """Whole solves with the one-launch-per-level sweeps (graph-captured),
+    with the checks of the other solve cases."""
+    monkeypatch.setenv("MPK_TRSV_MODE", "s")
+    p = case(name)
     b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K))
     ref = orc.krylov(method, p.row_ptr, p.col_idx, p.val, b, kf=kf, tol_rel=tol, max_iter=3000,
                      hist_len=3000)

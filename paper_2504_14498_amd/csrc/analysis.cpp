@@ -207,6 +207,94 @@ int32_t greedy_color(const HostCsr &h, IVec &color) {
   return ncol;
 }
 
+bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
+  const int64_t n = h.n;
+  if (n < 4) return false;
+  // strides from the last row's lower columns: 1, nx (2D) and nx ny (3D)
+  std::vector<int64_t> d;
+  for (int32_t p = h.rp[n - 1]; p < h.rp[n] && h.ci[p] < n - 1; ++p) d.push_back(n - 1 - h.ci[p]);
+  std::sort(d.begin(), d.end());
+  if (d.empty() || d[0] != 1) return false;
+  int64_t gx, gy, gz;
+  if (d.size() == 2) {
+    gx = d[1];
+    if (gx < 2 || n % gx) return false;
+    gy = n / gx;
+    gz = 1;
+  } else if (d.size() == 3) {
+    gx = d[1];
+    const int64_t pl = d[2];
+    if (gx < 2 || pl % gx || n % pl) return false;
+    gy = pl / gx;
+    gz = n / pl;
+    if (gz < 2) return false;
+  } else {
+    return false;
+  }
+  if (gy < 2) return false;
+  const int64_t pl = gx * gy;
+  // every row stores exactly its neighbours inside the grid (and its
+  // diagonal), ascending; checked on up to 8 host threads
+  const int T = int(std::min<int64_t>(8, std::max<int64_t>(1, n / 65536)));
+  std::vector<char> ok(size_t(T), 1);
+  auto work = [&](int t) {
+    const int64_t i0 = n * t / T, i1 = n * (t + 1) / T;
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t x = i % gx, y = (i / gx) % gy, z = i / pl;
+      int64_t want[7];
+      int m = 0;
+      if (z > 0) want[m++] = i - pl;
+      if (y > 0) want[m++] = i - gx;
+      if (x > 0) want[m++] = i - 1;
+      want[m++] = i;
+      if (x < gx - 1) want[m++] = i + 1;
+      if (y < gy - 1) want[m++] = i + gx;
+      if (z < gz - 1) want[m++] = i + pl;
+      if (h.rp[i + 1] - h.rp[i] != m) {
+        ok[t] = 0;
+        return;
+      }
+      for (int k = 0; k < m; ++k)
+        if (h.ci[h.rp[i] + k] != want[k]) {
+          ok[t] = 0;
+          return;
+        }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  for (int t = 0; t < T; ++t)
+    if (!ok[t]) return false;
+  nx = int32_t(gx);
+  ny = int32_t(gy);
+  nz = int32_t(gz);
+  return true;
+}
+
+void build_plan_grid(int64_t n, int kind, HostPlan &p) {
+  GridDims &g = p.grid;
+  const int by = g.nz > 1 ? 8 : 64, bz = 64 / by;
+  p.grid_by = by;
+  g.nby = (g.ny + by - 1) / by;
+  g.nbz = (g.nz + bz - 1) / bz;
+  p.nblk = g.nby * g.nbz;
+  // rows that the next block in y or in z reads, in the sweep's (for U
+  // mirrored) coordinates: the last line of a block in y or in z
+  p.xlist.clear();
+  const int64_t pl = int64_t(g.nx) * g.ny;
+  for (int64_t z = 0; z < g.nz; ++z)
+    for (int64_t y = 0; y < g.ny; ++y) {
+      const bool pub = (y % by == by - 1 && y < g.ny - 1) || (z % bz == bz - 1 && z < g.nz - 1);
+      if (!pub) continue;
+      for (int64_t x = 0; x < g.nx; ++x) {
+        const int64_t s = z * pl + y * g.nx + x;
+        p.xlist.push_back(int32_t(kind == 1 ? n - 1 - s : s));
+      }
+    }
+}
+
 // Rows per block of the blocked schedule: the block's results live in LDS,
 // at most 128 KiB for quad-double (K = 4).
 int default_block_rows(int C, int kmax) {
@@ -339,7 +427,7 @@ void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_ro
   // p.mode was set by plan_mode.  Global levels are needed by the level
   // schedule and, for the L sweep, by the factorisation; a blocked sweep
   // of U, U^H or L^H needs none.
-  if (p.mode == 1 && kind != 0) {
+  if ((p.mode == 1 || p.mode == 3) && kind != 0) {
     p.nlev = 0;
     return;
   }
@@ -374,7 +462,7 @@ void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_ro
     const bool force = e && e[0] == 's', forbid = e && e[0] == 'l';
     if (force || (!forbid && nlev <= 64 && n >= int64_t(nlev) * 16384)) p.mode = 2;
   }
-  if (p.mode != 1) {
+  if (p.mode == 0 || p.mode == 2) {
     counting_order(p.levptr, p.order);
     p.seg.clear();
     p.seg_level.clear();
@@ -598,8 +686,20 @@ int upload_plan(const HostPlan &hp, Plan &p, hipStream_t s) {
   p.blk_rows = hp.blk_rows;
   p.max_piece = hp.max_piece;
   p.geom = hp.geom;
-  MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * p.n, hipMemcpyHostToDevice, s));
   (void)n;
+  if (hp.mode != 3)
+    MPK_HIP(hipMemcpyAsync(p.order, hp.order.data(), sizeof(int32_t) * p.n,
+                           hipMemcpyHostToDevice, s));
+  if (hp.mode == 3) {
+    p.grid = hp.grid;
+    p.grid_by = hp.grid_by;
+    p.nx = int64_t(hp.xlist.size());
+    p.h_blk.assign(hp.xlist.begin(), hp.xlist.end());
+    if (p.nx > 0)
+      MPK_HIP(hipMemcpyAsync(p.xlist, p.h_blk.data(), sizeof(int32_t) * size_t(p.nx),
+                             hipMemcpyHostToDevice, s));
+    return MPK_OK;
+  }
   if (hp.mode == 1) {
     p.nloc = int32_t(hp.loc_pos.size()) - 1;
     p.h_blk.clear();

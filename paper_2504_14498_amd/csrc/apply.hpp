@@ -14,6 +14,36 @@ namespace mpk {
 template <int C, int K, int KF, bool DIV, bool CONJ>
 inline void launch_trsv(const Plan &P, const double *rhs, double *out, int32_t *abort_flag,
                         const int32_t *done, hipStream_t s) {
+  if constexpr (!CONJ) {
+    if (P.mode == 3) {
+      // grid sweep: the forward one for L, the backward one (dividing) for U
+      static const int64_t gcap = [] {
+        const char *e = getenv("MPK_TRSV_GGRID");
+        return e ? std::max<int64_t>(1, atoll(e)) : int64_t(512);
+      }();
+      const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(P.nblk, gcap)));
+      // the block's results staged in LDS when they fit
+      const size_t lds = grid_lds_bytes(P.grid.nx, C * K);
+      const bool stage = lds <= GRID_LDS_MAX;
+      auto go = [&]<int BY, bool ST>() {
+        hipLaunchKernelGGL((trsv_grid<C, K, KF, DIV, BY, ST>), dim3(grid), dim3(WAVE),
+                           ST ? lds : 0, s, P.n, P.grid, (const double *)P.ell_val, rhs, out,
+                           P.sync, abort_flag, done);
+      };
+      if (P.grid_by == 8) {
+        if (stage)
+          go.template operator()<8, true>();
+        else
+          go.template operator()<8, false>();
+      } else {
+        if (stage)
+          go.template operator()<64, true>();
+        else
+          go.template operator()<64, false>();
+      }
+      return;
+    }
+  }
   if (P.mode == 2) {
     // one launch per level, in order
     for (int32_t l = 0; l < P.nlev; ++l) {
@@ -69,12 +99,12 @@ inline int apply_ckf(const Ilu0 &M, int conj, const double *r, double *z, int32_
                      int32_t *abort_flag, const int32_t *done, hipStream_t s) {
   const Plan &P1 = conj ? M.UH : M.L;
   const Plan &P2 = conj ? M.LH : M.U;
-  // blocked sweeps poll only the rows other blocks read; level sweeps poll
-  // every row
-  const int32_t *l1 = P1.mode == 1 ? P1.xlist : nullptr, *l2 = P2.mode == 1 ? P2.xlist : nullptr;
-  // level-synchronous sweeps (mode 2) poll nothing
-  const int64_t c1 = P1.mode == 1 ? P1.nx : (P1.mode == 2 ? 0 : M.n),
-                c2 = P2.mode == 1 ? P2.nx : (P2.mode == 2 ? 0 : M.n);
+  // blocked and grid sweeps poll only listed rows; level-synchronous
+  // sweeps (mode 2) poll nothing
+  const bool x1 = P1.mode == 1 || P1.mode == 3, x2 = P2.mode == 1 || P2.mode == 3;
+  const int32_t *l1 = x1 ? P1.xlist : nullptr, *l2 = x2 ? P2.xlist : nullptr;
+  const int64_t c1 = x1 ? P1.nx : (P1.mode == 2 ? 0 : M.n),
+                c2 = x2 ? P2.nx : (P2.mode == 2 ? 0 : M.n);
   const int64_t cover = std::max<int64_t>(std::max(c1, c2) * C * K, std::max(P1.nlev, P2.nlev));
   hipLaunchKernelGGL(trsv_prep, dim3(nblocks(std::max<int64_t>(cover, 1))), dim3(BLOCK), 0, s,
                      C * K, l1, c1, M.tmp, l2, c2, z, P1.nlev, P1.lev_done, P2.nlev, P2.lev_done,

@@ -95,6 +95,13 @@ struct BlockGeom {
 // A dependency-ordered schedule for one triangular sweep: rows grouped by
 // level; `seg` splits each level into runs of at most WAVE rows (the work
 // unit of one wavefront, free of internal dependencies).
+// Grid of a grid sweep (mode 3): nx x ny x nz points numbered x fastest
+// (nz = 1 in 2D), cut into nby x nbz blocks of lines.
+struct GridDims {
+  int32_t nx = 0, ny = 0, nz = 0;
+  int32_t nby = 0, nbz = 0;
+};
+
 struct Plan {
   int64_t n = 0, nnz = 0;      // rows, dependency entries
   int32_t nlev = 0, nseg = 0;
@@ -112,7 +119,12 @@ struct Plan {
   int32_t *sync = nullptr;     // [0] ticket, [1] watchdog abort
   // blocked schedule (mode 1): contiguous row blocks in processing order,
   // each with its own local levels; positions are block-major
-  int32_t mode = 0;            // 0 level schedule, 1 blocked schedule, 2 one launch per level
+  int32_t mode = 0;            // 0 level schedule, 1 blocked schedule, 2 one launch per level,
+                               // 3 grid sweep
+  // grid sweep (mode 3): the grid and the lines per block in y (8 in 3D,
+  // 64 in 2D); ell_val holds each row's factor record (4 slots)
+  GridDims grid;
+  int32_t grid_by = 0;
   int32_t nblk = 0, nloc = 0;  // blocks, local levels in total
   int32_t kmax = 4;            // largest vector precision the blocks are sized for
   int32_t blk_rows = 0;        // LDS slots per block (t * w)
@@ -255,6 +267,9 @@ struct HostPlan {
   BlockGeom geom;
   std::vector<int32_t> blk_r, blk_lev, loc_pos;
   std::vector<int32_t> glob_order, glob_levptr;  // global level order (factorisation)
+  GridDims grid;                 // grid sweep (mode 3)
+  int32_t grid_by = 0;
+  std::vector<int32_t> xlist;    // grid sweep: rows read by later blocks
 };
 // kind: 0 = L (strict lower of rows, forward), 1 = U (strict upper, backward,
 // divides), 2 = U^H (columns of the upper part, forward, divides),
@@ -267,6 +282,13 @@ void build_plan(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows, Hos
 // chosen.  With p.mode set, the last two touch different fields of p and
 // may run on different threads.
 int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows);
+// The pattern is the 7-point (3D) or 5-point (2D) stencil of an nx x ny x
+// nz grid numbered x fastest (every row stores exactly its neighbours
+// inside the grid): the L and U sweeps can be grid sweeps (mode 3).
+bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz);
+// Grid sweep plan of the L (kind 0) or U (kind 1) sweep: block counts and
+// the rows that later blocks read (p.mode = 3 and the grid set before).
+void build_plan_grid(int64_t n, int kind, HostPlan &p);
 void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
                        HostPlan &p);
 void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,

@@ -1022,6 +1022,381 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
   }
 }
 
+// ---- grid sweep (mode 3) -------------------------------------------------
+// For a matrix whose pattern is the 7-point (3D) or 5-point (2D) stencil of
+// an nx x ny x nz grid numbered x fastest, the L sweep (forward) and the U
+// sweep (backward, dividing by the pivot) need no schedule arrays: a block
+// is BY grid lines in y times BZ in z (BY * BZ = 64, one wavefront), the
+// lane of line (yl, zl) is q = zl + BZ yl, and at local level l the lane
+// handles x = l - yl - zl.  The dependency on x - 1 is then the lane's own
+// value of the previous level, the ones on z - 1 and y - 1 inside the block
+// are the previous level's values of lanes q - 1 (a DPP shift) and q - BZ
+// (ds_bpermute), and those in the blocks below come from memory with the
+// sentinel-checked wait.  The backward sweep runs the same walk on the
+// mirrored grid (row n - 1 - i).  Blocks are taken from a ticket in sweep
+// order (z-block major), so a block waits only on taken blocks.  Each
+// row's terms are subtracted in ascending column order (z, y, x forward;
+// x, y, z backward, mirrored) and the row arithmetic is the level
+// schedule's.
+//
+// Memory: the factor values come from records made at setup (grid_gather),
+// one per row in processing order (block, level, then active lane), so a
+// level's records are contiguous and its loads coalesce.  Rows that a later
+// block reads are stored at agent scope as they are finished; the block's
+// results also go to LDS (line q at slot q (nx + 1) + x) and are copied to
+// memory, line by line, when the block ends (STAGE), or, when the block
+// does not fit in LDS, stored at once.
+
+template <int C, int K, int KF> struct GridRow {
+  double f[4][C * KF];       // term values in term order; [3] the pivot (backward)
+  el<C, K> rh;               // right-hand side
+  el<C, K> ye[2];            // external y - 1 and z - 1 values
+};
+
+template <int BY> constexpr int grid_bz() { return WAVE / BY; }
+template <int E> constexpr int grid_depth() { return E <= 2 ? 8 : 4; }
+template <int E> constexpr int grid_lead() { return E <= 2 ? 3 : 2; }
+
+// Rows of the grid sweep's blocks before block (by, bz): whole z-slabs of
+// BZ ny lines below bz, then by blocks of BY x lz lines in slab bz.
+__host__ __device__ __forceinline__ int64_t grid_block_start(const GridDims &g, int by_, int bz_,
+                                                             int32_t by, int32_t bz) {
+  const int64_t lz = min(int64_t(bz_), int64_t(g.nz) - int64_t(bz) * bz_);
+  return (int64_t(bz) * bz_ * g.ny + lz * int64_t(by) * by_) * g.nx;
+}
+
+// The factor records of a grid sweep: record pos holds the row's three
+// term values in term order (zero where the neighbour is outside the grid)
+// and, backward, its pivot, C * KF doubles each, at gval[(pos * 4 + slot)
+// * C * KF].  pos numbers the rows in processing order: block start, then
+// the rows of the block's earlier levels, then the active lanes before the
+// row's lane at its level (by = lines per block in y).
+static __global__ void grid_gather(int64_t n, GridDims g, int by_, int back, int V,
+                                   const int32_t *__restrict__ diag,
+                                   const double *__restrict__ f, double *__restrict__ gval) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int bz_ = WAVE / by_;
+  const int64_t s = back ? n - 1 - i : i;  // sweep coordinates
+  const int64_t pl = int64_t(g.nx) * g.ny;
+  const int64_t x = s % g.nx, y = (s / g.nx) % g.ny, z = s / pl;
+  const int32_t by = int32_t(y / by_), bz = int32_t(z / bz_);
+  const int yl = int(y % by_), zl = int(z % bz_), q = zl + bz_ * yl;
+  const int64_t l = x + yl + zl;
+  int64_t pos = grid_block_start(g, by_, bz_, by, bz);
+  for (int q2 = 0; q2 < WAVE; ++q2) {
+    const int yl2 = q2 / bz_, zl2 = q2 % bz_;
+    if (int64_t(by) * by_ + yl2 >= g.ny || int64_t(bz) * bz_ + zl2 >= g.nz) continue;
+    const int64_t c = yl2 + zl2;
+    pos += min(max(l - c, int64_t(0)), int64_t(g.nx));   // its rows at levels below l
+    if (q2 < q && l - c >= 0 && l - c < g.nx) ++pos;      // active before this lane at l
+  }
+  const bool ex = x > 0, ey = y > 0, ez = z > 0;
+  const int64_t dg = diag[i];
+  int64_t p[3];
+  bool has[3];
+  if (!back) {
+    // stored lower entries z-1, y-1, x-1 just before the diagonal
+    const int nlow = int(ex) + int(ey) + int(ez);
+    has[0] = ez;
+    has[1] = ey;
+    has[2] = ex;
+    p[0] = dg - nlow;
+    p[1] = dg - nlow + int(ez);
+    p[2] = dg - 1;
+  } else {
+    // stored upper entries x+1, y+1, z+1 just after it (mirrored: x-1, y-1, z-1)
+    has[0] = ex;
+    has[1] = ey;
+    has[2] = ez;
+    p[0] = dg + 1;
+    p[1] = dg + 1 + int(ex);
+    p[2] = dg + 1 + int(ex) + int(ey);
+  }
+  double *o = gval + pos * 4 * V;
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < V; ++v) o[d * V + v] = has[d] ? f[p[d] * V + v] : 0.0;
+  for (int v = 0; v < V; ++v) o[3 * V + v] = back ? f[dg * V + v] : 0.0;
+}
+
+// N doubles from byte offset o of a buffer: 16-byte loads when N is even
+// (o a multiple of 16), else 8-byte loads.
+template <int N, int AUX>
+__device__ __forceinline__ void buf_ld_n(__amdgpu_buffer_rsrc_t r, uint32_t o, double *d) {
+  if constexpr (N % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const bu4 w = __builtin_amdgcn_raw_buffer_load_b128(r, int(o + uint32_t(j * 16)), 0, AUX);
+      d[2 * j] = __builtin_bit_cast(double, (uint64_t(w.y) << 32) | w.x);
+      d[2 * j + 1] = __builtin_bit_cast(double, (uint64_t(w.w) << 32) | w.z);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) d[j] = buf_ld<AUX>(r, o + uint32_t(j * 8));
+  }
+}
+
+template <int C, int K>
+__device__ __forceinline__ void el_ld(__amdgpu_buffer_rsrc_t r, uint32_t o, el<C, K> &v) {
+  double d[C * K];
+  buf_ld_n<C * K, 0>(r, o, d);
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v.c[c].v[k] = d[c * K + k];
+}
+
+template <int C, int K>
+__device__ __forceinline__ void el_ld_agent(__amdgpu_buffer_rsrc_t r, uint32_t o, el<C, K> &v) {
+  double d[C * K];
+  buf_ld_n<C * K, BUF_AGENT>(r, o, d);
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v.c[c].v[k] = d[c * K + k];
+}
+
+// Lane q - 1's copy of v (lane 0 gets zero): one DPP move per dword.
+template <int C, int K>
+__device__ __forceinline__ el<C, K> lane_prev(const el<C, K> &v) {
+  el<C, K> r;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t b = __builtin_bit_cast(uint64_t, v.c[c].v[k]);
+      const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), 0x138, 0xf, 0xf, true));
+      const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), 0x138, 0xf, 0xf, true));
+      r.c[c].v[k] = __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+    }
+  return r;
+}
+
+// Lane src's copy of v (ds_bpermute).
+template <int C, int K>
+__device__ __forceinline__ el<C, K> lane_read(const el<C, K> &v, int src) {
+  el<C, K> r;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t b = __builtin_bit_cast(uint64_t, v.c[c].v[k]);
+      const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src * 4, int(uint32_t(b))));
+      const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src * 4, int(uint32_t(b >> 32))));
+      r.c[c].v[k] = __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+    }
+  return r;
+}
+
+template <int C, int K>
+__device__ __forceinline__ bool el_has_sentinel(const el<C, K> &v) {
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) bad = bad | (__builtin_bit_cast(uint64_t, v.c[c].v[k]) == SENTINEL);
+  return bad;
+}
+
+template <int C, int K>
+__device__ __forceinline__ el<C, K> el_select(bool p, const el<C, K> &a, const el<C, K> &b) {
+  el<C, K> r;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.c[c].v[k] = p ? a.c[c].v[k] : b.c[c].v[k];
+  return r;
+}
+
+// LDS bytes of a grid sweep block staged in LDS: 64 lines of nx + 1 slots
+// (the extra slot keeps consecutive lines in different banks) and a spare
+// slot for lanes without a row.
+inline size_t grid_lds_bytes(int32_t nx, int E) {
+  return (size_t(WAVE) * (size_t(nx) + 1) + 1) * size_t(E) * 8;
+}
+constexpr size_t GRID_LDS_MAX = 159 * 1024;  // below the 160 KiB of a CU
+
+template <int C, int K, int KF, bool BACK, int BY, bool STAGE>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) void trsv_grid(
+    int64_t n, GridDims g, const double *__restrict__ gval, const double *__restrict__ rhs,
+    double *out, int32_t *ticket, int32_t *abort_flag, const int32_t *done) {
+  if (done && *done) return;
+  extern __shared__ double lds[];
+  constexpr int BZ = grid_bz<BY>();
+  constexpr int E = C * K;
+  constexpr int V = C * KF;
+  constexpr int D = grid_depth<E>();
+  constexpr int X = grid_lead<E>();  // levels ahead at which external values are requested
+  using GR = GridRow<C, K, KF>;
+  __shared__ int32_t cur;
+  const int q = int(threadIdx.x);
+  const int zl = q % BZ, yl = q / BZ;
+  const int64_t plane = int64_t(g.nx) * g.ny;
+  const int32_t stride = g.nx + 1;                 // LDS slots per line
+  const int32_t spare = WAVE * stride;            // LDS slot of lanes without a row
+  const __amdgpu_buffer_rsrc_t Rg = buf_rsrc(gval, n * 4 * V * 8);
+  const __amdgpu_buffer_rsrc_t Rr = buf_rsrc(rhs, n * E * 8);
+  const __amdgpu_buffer_rsrc_t Ro = buf_rsrc(out, n * E * 8);
+  for (;;) {
+    if (q == 0) cur = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int32_t b = cur;
+    __syncthreads();
+    if (b >= g.nby * g.nbz) break;
+    const int32_t by = b % g.nby, bz = b / g.nby;
+    // this lane's line, in sweep coordinates (mirrored when BACK)
+    const int32_t y = by * BY + yl, z = bz * BZ + zl;
+    const bool line = y < g.ny && z < g.nz;
+    const int64_t base = int64_t(z) * plane + int64_t(y) * g.nx;  // row of x = 0
+    const bool ey = y > 0, ez = z > 0;
+    const bool exty = ey && yl == 0, extz = ez && zl == 0;  // neighbour in another block
+    // stored at agent scope: read by the next block in y or in z
+    const bool pub = line && ((yl == BY - 1 && y < g.ny - 1) || (zl == BZ - 1 && z < g.nz - 1));
+    const int32_t nlev = g.nx + (BY - 1) + (BZ - 1);
+    auto real = [&](int64_t s) { return BACK ? n - 1 - s : s; };
+    auto active = [&](int32_t l) {
+      const int32_t x = l - yl - zl;
+      return line && x >= 0 && x < g.nx;
+    };
+    // position of the next staged level's first record
+    int64_t run = grid_block_start(g, BY, BZ, by, bz);
+    // row data, D levels ahead: the factor record and the right-hand side
+    auto stage_row = [&](GR &r, int32_t l) {
+      const bool a = active(l);
+      const uint64_t m = __ballot(a);
+      const int64_t pos = run + int64_t(__builtin_amdgcn_mbcnt_hi(
+                                    uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
+      run += __popcll(m);
+      const uint32_t og = a ? uint32_t(pos) * uint32_t(4 * V * 8) : BUF_OOB;
+      double fr[4 * V];
+      buf_ld_n<(BACK ? 4 : 3) * V, 0>(Rg, og, fr);
+#pragma unroll
+      for (int d = 0; d < (BACK ? 4 : 3); ++d)
+#pragma unroll
+        for (int v = 0; v < V; ++v) r.f[d][v] = fr[d * V + v];
+      const uint32_t o = a ? uint32_t(real(base + (l - yl - zl))) * uint32_t(E * 8) : BUF_OOB;
+      el_ld<C, K>(Rr, o, r.rh);
+    };
+    // external neighbours, X levels ahead
+    auto stage_ext = [&](GR &r, int32_t l) {
+      const bool a = active(l);
+      const int64_t is = base + (l - yl - zl);
+      const uint32_t oy = (a && exty) ? uint32_t(real(is - g.nx)) * uint32_t(E * 8) : BUF_OOB;
+      const uint32_t oz = (a && extz) ? uint32_t(real(is - plane)) * uint32_t(E * 8) : BUF_OOB;
+      el_ld_agent<C, K>(Ro, oy, r.ye[0]);
+      el_ld_agent<C, K>(Ro, oz, r.ye[1]);
+    };
+    GR st[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) stage_row(st[u], u);
+#pragma unroll
+    for (int u = 0; u < X; ++u) stage_ext(st[u], u);
+    el<C, K> prev = el_zero<C, K>();  // this lane's value of the previous level
+    // finish level l from its staged data, then request the external values
+    // of level l + X and the row data of level l + D
+    auto level = [&](GR &now, GR &ext, int32_t l) {
+      const bool a = active(l);
+      const int32_t x = l - yl - zl;
+      // neighbours inside the block: the previous level's values
+      el<C, K> vy, vz = el_zero<C, K>();
+      if constexpr (BZ == 1) {
+        vy = lane_prev<C, K>(prev);
+      } else {
+        vz = lane_prev<C, K>(prev);
+        vy = lane_read<C, K>(prev, q >= BZ ? q - BZ : 0);
+      }
+      if (int(el_has_sentinel<C, K>(now.ye[0])) | int(el_has_sentinel<C, K>(now.ye[1]))) {
+        // external words not written yet: re-poll them (bounded)
+        const int64_t is = base + x;
+        for (int it = 0;; ++it) {
+          const bool my = a && exty && el_has_sentinel<C, K>(now.ye[0]);
+          const bool mz = a && extz && el_has_sentinel<C, K>(now.ye[1]);
+          if (!(my | mz)) break;
+          const uint32_t oy = my ? uint32_t(real(is - g.nx)) * uint32_t(E * 8) : BUF_OOB;
+          const uint32_t oz = mz ? uint32_t(real(is - plane)) * uint32_t(E * 8) : BUF_OOB;
+          el<C, K> wy, wz;
+          el_ld_agent<C, K>(Ro, oy, wy);
+          el_ld_agent<C, K>(Ro, oz, wz);
+          now.ye[0] = el_select<C, K>(my, wy, now.ye[0]);
+          now.ye[1] = el_select<C, K>(mz, wz, now.ye[1]);
+          if ((it & 63) == 63 && ld_agent_i(abort_flag)) break;
+          if (it >= SPIN_LIMIT) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      el<C, K> acc = now.rh;
+      // term order: forward z, y, x; backward x, y, z (mirrored)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int which = BACK ? d : 2 - d;  // 0 = x, 1 = y, 2 = z
+        bool has;
+        el<C, K> yv;
+        if (which == 0) {
+          has = x > 0;
+          yv = prev;
+        } else if (which == 1) {
+          has = ey;
+          yv = el_select<C, K>(exty, now.ye[0], vy);
+        } else {
+          has = ez;
+          yv = el_select<C, K>(extz, now.ye[1], vz);
+        }
+        const el<C, K> t = el_sub<C, K>(acc, el_mul_f<C, K, KF>(now.f[d], yv));
+        acc = el_select<C, K>(has, t, acc);
+      }
+      if constexpr (BACK) acc = el_div_k<C, K, KF>(acc, now.f[3]);
+      const uint32_t o = a ? uint32_t(real(base + x)) * uint32_t(E * 8) : BUF_OOB;
+      double *slot = lds + size_t(a ? q * stride + x : spare) * E;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          double v = acc.c[c].v[k];
+          v = v != v ? __builtin_nan("") : v;
+          acc.c[c].v[k] = v;
+          const uint32_t oo = o + uint32_t((c * K + k) * 8);
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Ro,
+                                                int(pub ? oo : BUF_OOB), 0, BUF_AGENT);
+          if constexpr (STAGE)
+            slot[c * K + k] = v;
+          else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Ro,
+                                                  int(pub ? BUF_OOB : oo), 0, 0);
+        }
+      prev = el_select<C, K>(a, acc, prev);
+      stage_ext(ext, l + X);
+      stage_row(now, l + D);
+    };
+    for (int32_t lv = 0; lv < nlev; lv += D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) level(st[u], st[(u + X) % D], lv + u);
+    }
+    if constexpr (STAGE) {
+      // the block's results from LDS to memory, line by line (one wavefront:
+      // its LDS operations execute in order, so no barrier is needed)
+      asm volatile("" ::: "memory");
+      for (int ql = 0; ql < WAVE; ++ql) {
+        const int32_t y2 = by * BY + ql / BZ, z2 = bz * BZ + ql % BZ;
+        if (y2 >= g.ny || z2 >= g.nz) continue;
+        const int64_t b2 = int64_t(z2) * plane + int64_t(y2) * g.nx;
+        for (int32_t x2 = q; x2 < g.nx; x2 += WAVE) {
+          const double *src = lds + size_t(ql * stride + x2) * E;
+          const uint32_t o2 = uint32_t(real(b2 + x2)) * uint32_t(E * 8);
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, src[e]), Ro,
+                                                  int(o2 + uint32_t(e * 8)), 0, 0);
+        }
+      }
+      asm volatile("" ::: "memory");
+    }
+    __syncthreads();
+  }
+}
+
 // Prepares one apply: the words that other workgroups poll filled with
 // SENTINEL (rows list1[0..cnt1) of out1 and list2[0..cnt2) of out2, or
 // rows 0..cnt-1 when a list is null: the level schedule polls every row),

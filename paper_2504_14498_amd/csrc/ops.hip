@@ -126,6 +126,11 @@ static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
 // Per-position schedule arrays of a plan, built on the device from the
 // uploaded row order (count, scan, fill).
 static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
+  if (P.mode == 3) {
+    // grid sweeps need only their factor records (gather_plan)
+    P.nnz = 0;
+    return MPK_OK;
+  }
   const int64_t n = P.n;
   const bool tr = kind >= 2;
   const int32_t *rp = tr ? M.t_rp : M.row_ptr, *ci = tr ? M.t_ci : M.col_idx;
@@ -170,6 +175,15 @@ static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
 }
 
 static int gather_plan(const Plan &P, const Ilu0 &M, hipStream_t s) {
+  if (P.mode == 3) {
+    // grid sweep: each row's term values (and pivot) in one record
+    if (P.n > 0)
+      hipLaunchKernelGGL(grid_gather, dim3(nblocks(P.n)), dim3(BLOCK), 0, s, P.n, P.grid,
+                         P.grid_by, P.div ? 1 : 0, M.C * M.KF, (const int32_t *)M.diag,
+                         (const double *)M.f, P.ell_val);
+    MPK_HIP(hipGetLastError());
+    return MPK_OK;
+  }
   if (P.mode == 1 && P.n > 0)
     hipLaunchKernelGGL(gather_vals, dim3(nblocks(P.n * ELLW)), dim3(BLOCK), 0, s, P.n * ELLW, M.C,
                        M.KF, P.ell_src, M.f, P.ell_val, 0);
@@ -252,9 +266,36 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     // device while the blocked schedules are built on the host; the forward
     // sweep's blocked schedule needs only the schedule choice and is built
     // on its own thread meanwhile.
-    hp[0].mode = plan_mode(h, nullptr, 0, br);
-    std::thread t0([&] { build_plan_blocks(h, nullptr, 0, br, hp[0]); });
-    std::thread t1([&] { build_plan(h, nullptr, 1, br, hp[1]); });
+    // a 7-point or 5-point grid numbered x fastest: grid sweeps for L and U
+    // (MPK_TRSV_MODE forces the other schedules)
+    const char *force = getenv("MPK_TRSV_MODE");
+    int32_t gx = 0, gy = 0, gz = 0;
+    const bool grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
+                      A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
+                      A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31) &&
+                      detect_grid(h, gx, gy, gz);
+    if (grid) {
+      for (int k = 0; k < 2; ++k) {
+        hp[k].mode = 3;
+        hp[k].grid.nx = gx;
+        hp[k].grid.ny = gy;
+        hp[k].grid.nz = gz;
+      }
+    } else {
+      hp[0].mode = plan_mode(h, nullptr, 0, br);
+    }
+    std::thread t0([&] {
+      if (grid)
+        build_plan_grid(h.n, 0, hp[0]);
+      else
+        build_plan_blocks(h, nullptr, 0, br, hp[0]);
+    });
+    std::thread t1([&] {
+      if (grid)
+        build_plan_grid(h.n, 1, hp[1]);
+      else
+        build_plan(h, nullptr, 1, br, hp[1]);
+    });
     std::thread t2;
     if (adj) {
       t2 = std::thread([&] {

@@ -166,6 +166,43 @@ void check_color(const HostCsr &h, const HostCsr &t) {
   }
 }
 
+// Grid sweeps: detect_grid on stencils (with the grid's shape) and on
+// other patterns (rejected); the rows a grid sweep's blocks read from
+// other blocks (the y - 1 and z - 1 neighbours of a block's first lines,
+// in the sweep's coordinates) are all in the plan's list, and the list
+// holds rows in range, each once.
+void check_grid(const HostCsr &h, int nx, int ny, int nz, bool expect) {
+  int32_t gx = -1, gy = -1, gz = -1;
+  const bool got = detect_grid(h, gx, gy, gz);
+  EXPECT(got == expect);
+  if (!got) return;
+  EXPECT(gx == nx && gy == ny && gz == nz);
+  for (int kind = 0; kind < 2; ++kind) {
+    HostPlan hp;
+    hp.mode = 3;
+    hp.grid.nx = gx;
+    hp.grid.ny = gy;
+    hp.grid.nz = gz;
+    build_plan_grid(h.n, kind, hp);
+    const int by = hp.grid_by, bz = 64 / by;
+    EXPECT(by * bz == 64 && hp.grid.nby * by >= ny && hp.grid.nbz * bz >= nz);
+    std::vector<char> in(size_t(h.n), 0);
+    for (int32_t r : hp.xlist) {
+      EXPECT(r >= 0 && r < h.n && !in[r]);
+      in[r] = 1;
+    }
+    const int64_t pl = int64_t(nx) * ny;
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t y = 0; y < ny; ++y)
+        for (int64_t x = 0; x < nx; ++x) {
+          const int64_t s = z * pl + y * nx + x;
+          auto real = [&](int64_t v) { return kind == 1 ? h.n - 1 - v : v; };
+          if (y > 0 && y % by == 0) EXPECT(in[real(s - nx)]);
+          if (z > 0 && z % bz == 0) EXPECT(in[real(s - pl)]);
+        }
+  }
+}
+
 void run(const Pattern &pat, const char *name) {
   const HostCsr h = view(pat);
   int64_t bad = -2;
@@ -223,6 +260,20 @@ void bad_patterns() {
 }  // namespace
 
 int main() {
+  check_grid(view(stencil(20, 13, 9)), 20, 13, 9, true);
+  check_grid(view(stencil(9, 17, 16)), 9, 17, 16, true);
+  check_grid(view(stencil(45, 33, 1)), 45, 33, 1, true);
+  check_grid(view(stencil(64, 70, 1)), 64, 70, 1, true);
+  check_grid(view(stencil(37, 1, 1)), 37, 1, 1, false);   // 1D: not a grid sweep
+  check_grid(view(random_pattern(3001, 9, 5)), 0, 0, 0, false);
+  {
+    // a stencil with one entry missing is not a grid
+    Pattern p = stencil(12, 12, 12);
+    p.ci.erase(p.ci.begin() + 5000);
+    for (size_t k = 0; k < p.rp.size(); ++k)
+      if (p.rp[k] > 5000) --p.rp[k];
+    check_grid(view(p), 0, 0, 0, false);
+  }
   run(stencil(37, 1, 1), "tridiagonal");
   run(stencil(1, 1, 1), "one row");
   run(stencil(45, 33, 1), "5-point 45x33");

@@ -214,6 +214,7 @@ def test_ilu0_apply_deep_blocks_bitwise(mpk, orc, monkeypatch, shape, rows, kf, 
     3D and 2D grids and a complex system; all four sweeps (L, U and the
     adjoint pair) against the oracle, element by element."""
     monkeypatch.setenv("MPK_TRSV_BLOCK_ROWS", str(rows))
+    monkeypatch.setenv("MPK_TRSV_MODE", "b")   # blocked, not the grid sweeps
     if shape == "conv3d_20":
         p = W.config2(20)
         rp, ci, val, C = p.row_ptr, p.col_idx, p.val, 1
@@ -233,6 +234,81 @@ def test_ilu0_apply_deep_blocks_bitwise(mpk, orc, monkeypatch, shape, rows, kf, 
     assert np.array_equal(z, orc.ilu0_apply(rp, ci, f, r))
     zh = host(mpk.ilu0_apply(M, dev(r), conj_trans=True))
     assert np.array_equal(zh, orc.ilu0_apply(rp, ci, f, r, conj_trans=True))
+
+
+def grid_problem(shape, seed, C=1):
+    """A matrix on the 7-point (3D) or 5-point (2D) stencil of a grid of the
+    given shape (x fastest), random off-diagonal entries and a dominant
+    diagonal; complex when C = 2."""
+    rng = np.random.default_rng(seed)
+    dims = len(shape)
+    offs = ([(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+            if dims == 3 else [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)])
+    arr_shape = tuple(reversed(shape))
+    coef = []
+    for o in offs:
+        if all(v == 0 for v in o):
+            coef.append(None)
+            continue
+        c = -rng.uniform(0.1, 1.0, arr_shape)
+        if C == 2:
+            c = c + 1j * rng.uniform(-0.3, 0.3, arr_shape)
+        coef.append(c)
+    dia = sum(np.abs(c) for c in coef if c is not None) + 1.0
+    coef = [dia if c is None else c for c in coef]
+    rp, ci, val = W.stencil_csr(shape, offs, coef)
+    return rp, ci, val
+
+
+GRID_SHAPES = [(12, 12, 12), (20, 13, 9), (9, 17, 16), (33, 8, 8), (5, 3, 70), (37, 37),
+               (150, 150), (64, 70), (7, 200), (130, 65)]
+
+
+@pytest.mark.parametrize("shape", GRID_SHAPES)
+@pytest.mark.parametrize("kf,K", [(1, 1), (1, 2), (2, 2), (1, 3), (3, 3), (2, 4), (4, 4)])
+def test_ilu0_apply_grid_bitwise(mpk, orc, shape, kf, K):
+    """The grid sweeps (7-point and 5-point stencils numbered x fastest,
+    blocks of 8 x 8 or 64 lines, ragged last blocks) against the oracle,
+    element by element: the forward L and backward U sweeps, and the
+    adjoint pair (which keeps the blocked sweeps)."""
+    rp, ci, val = grid_problem(shape, sum(shape) + kf)
+    n = len(rp) - 1
+    A = mpk.Csr(rp, ci, val)
+    M = mpk.ilu0_factor(A, kf, adjoint=True)
+    st, bad, f = orc.ilu0(rp, ci, val, 1, kf)
+    assert st == 0
+    r = rand_vec(np.random.default_rng(5 * K + kf), n, 1, K)
+    assert np.array_equal(host(mpk.ilu0_apply(M, dev(r))), orc.ilu0_apply(rp, ci, f, r))
+    assert np.array_equal(host(mpk.ilu0_apply(M, dev(r), conj_trans=True)),
+                          orc.ilu0_apply(rp, ci, f, r, conj_trans=True))
+
+
+@pytest.mark.parametrize("shape", [(10, 11, 12), (70, 70), (9, 130)])
+@pytest.mark.parametrize("kf,K", [(1, 2), (2, 2), (1, 4), (4, 4)])
+def test_ilu0_apply_grid_complex_bitwise(mpk, orc, shape, kf, K):
+    rp, ci, val = grid_problem(shape, 3 + kf, C=2)
+    n = len(rp) - 1
+    A = mpk.Csr(rp, ci, val)
+    M = mpk.ilu0_factor(A, kf)
+    st, bad, f = orc.ilu0(rp, ci, val, 2, kf)
+    assert st == 0
+    r = rand_vec(np.random.default_rng(9 * K + kf), n, 2, K)
+    assert np.array_equal(host(mpk.ilu0_apply(M, dev(r))), orc.ilu0_apply(rp, ci, f, r))
+
+
+def test_ilu0_apply_grid_matches_blocked(mpk, orc, monkeypatch):
+    """On the same 24^3 system the grid sweeps and the forced blocked sweeps
+    give the same bits (and the oracle's)."""
+    rp, ci, val = grid_problem((24, 24, 24), 11)
+    n = len(rp) - 1
+    r = rand_vec(np.random.default_rng(1), n, 1, 2)
+    A = mpk.Csr(rp, ci, val)
+    z_grid = host(mpk.ilu0_apply(mpk.ilu0_factor(A, 1), dev(r)))
+    monkeypatch.setenv("MPK_TRSV_MODE", "b")
+    z_blk = host(mpk.ilu0_apply(mpk.ilu0_factor(A, 1), dev(r)))
+    st, bad, f = orc.ilu0(rp, ci, val, 1, 1)
+    assert np.array_equal(z_grid, z_blk)
+    assert np.array_equal(z_grid, orc.ilu0_apply(rp, ci, f, r))
 
 
 @pytest.mark.parametrize("C,K", [(1, 1), (1, 2), (1, 4), (2, 2), (2, 3)])
@@ -360,6 +436,7 @@ def test_solve_parity_deep_blocks(mpk, orc, monkeypatch, method, K, kf):
     blocks forced on a 20^3 grid, so sweeps cross many of them): the same
     checks as the other solve cases against the oracle."""
     monkeypatch.setenv("MPK_TRSV_BLOCK_ROWS", "256")
+    monkeypatch.setenv("MPK_TRSV_MODE", "b")   # blocked, not the grid sweeps
     p = W.config2(20)
     tol = 1e-25 if K == 2 else 1e-35
     b = orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(K))

@@ -106,6 +106,16 @@ int mpk_dcsr_spmv(mpk_prec xp, const mpk_csr *A, int trans, const double *x, dou
 int mpk_zcsr_spmv(mpk_prec xp, const mpk_csr *A, int conj_trans, const double *x, double *y,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* r = b - A x in the working precision p (the true residual that the
+ * solvers check, Algorithm 3's stopping rule): row i forms (A x)_i as the
+ * SpMV above, then subtracts it from b_i once.  b, x, r: device vectors of
+ * n elements of (z: 2, d: 1) * p doubles; r must not overlap x.
+ * Asynchronous on stream. */
+int mpk_dcsr_residual(mpk_prec p, const mpk_csr *A, const double *b, const double *x, double *r,
+                      void *stream);
+int mpk_zcsr_residual(mpk_prec p, const mpk_csr *A, const double *b, const double *x, double *r,
+                      void *stream);
+
 /* Lanes per row of the plain (non-transposed) SpMV for one matrix, keyed
  * by its row_ptr, col_idx and val pointers and n: 1 = one lane per row
  * (the default), 2, 4, 8 or 16 = vector CSR, where that many lanes load and

@@ -195,6 +195,18 @@ template <int C, int K> struct SpmvOp {
   }
 };
 
+// r = b - A x: the row's SpMV sum (row_spmv), then one subtraction from b_i
+// in the working precision.
+template <int C, int K> struct ResidOp {
+  const int32_t *rp, *ci;
+  const double *val, *b, *x;
+  double *r;
+  __device__ void operator()(int64_t i, el<C, K> *) const {
+    const el<C, K> bi = el_load<C, K>(b + size_t(i) * C * K);
+    el_store<C, K>(r + size_t(i) * C * K, el_sub<C, K>(bi, row_spmv<C, K>(i, rp, ci, val, x)));
+  }
+};
+
 // Gathers C binary64 values per entry, conjugating when asked (A^H).
 static __global__ void gather_vals(int64_t m, int C, int KF, const int32_t *__restrict__ src,
                             const double *__restrict__ from, double *__restrict__ to, int conj) {
@@ -1054,8 +1066,12 @@ template <int C, int K, int KF> struct GridRow {
 };
 
 template <int BY> constexpr int grid_bz() { return WAVE / BY; }
-template <int E> constexpr int grid_depth() { return E <= 2 ? 8 : 4; }
-template <int E> constexpr int grid_lead() { return E <= 2 ? 3 : 2; }
+template <int E> constexpr int grid_depth() { return E <= 2 ? 6 : 4; }
+// External values are requested two levels ahead: one level leaves the
+// load's latency exposed, three or more ask before the producer has
+// stored them and cost a re-poll (128^3 DD: 0.71, 0.59, 0.61, 0.66 ms per
+// apply for leads 1 to 4).
+template <int E> constexpr int grid_lead() { return 2; }
 
 // Rows of the grid sweep's blocks before block (by, bz): whole z-slabs of
 // BZ ny lines below bz, then by blocks of BY x lz lines in slab bz.

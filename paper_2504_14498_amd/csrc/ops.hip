@@ -614,6 +614,31 @@ int mpk_dot_noalloc(mpk_prec p, int is_complex, int64_t n, const double *a, cons
   });
 }
 
+static int csr_residual(int C, mpk_prec p, const mpk_csr *A, const double *b, const double *x,
+                        double *r, void *stream) {
+  int st = validate_csr_args(A);
+  if (st) return st;
+  if (p < MPK_D || p > MPK_QD || !b || !x || !r) return MPK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = A->n;
+  return dispatch_ck(C, int(p), [&]<int CC, int KK>() {
+    ResidOp<CC, KK> op{A->row_ptr, A->col_idx, A->val, b, x, r};
+    hipLaunchKernelGGL((row_kernel<CC, KK, 0, ResidOp<CC, KK>>), dim3(xcd_grid(nblocks(n))),
+                       dim3(BLOCK), 0, s, n, op, (const int32_t *)nullptr, (double *)nullptr);
+    return hipGetLastError() == hipSuccess ? MPK_OK : MPK_EDEVICE;
+  });
+}
+
+int mpk_dcsr_residual(mpk_prec p, const mpk_csr *A, const double *b, const double *x, double *r,
+                      void *stream) {
+  return csr_residual(1, p, A, b, x, r, stream);
+}
+
+int mpk_zcsr_residual(mpk_prec p, const mpk_csr *A, const double *b, const double *x, double *r,
+                      void *stream) {
+  return csr_residual(2, p, A, b, x, r, stream);
+}
+
 int mpk_spmv_set_lanes(const mpk_csr *A, int lanes) {
   if (validate_csr_args(A)) return MPK_EINVAL;
   if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))

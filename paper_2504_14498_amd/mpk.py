@@ -91,6 +91,8 @@ SIGNATURES = [
     ("mpk_dot", _I, [_I, _I, _I64, _P, _P, _P, _P, _S, _P]),
     ("mpk_dot_noalloc_max_elements", _S, [_I, _I]),
     ("mpk_dot_noalloc", _I, [_I, _I, _I64, _P, _P, _P, _P]),
+    ("mpk_dcsr_residual", _I, [_I, _CSRP, _P, _P, _P, _P]),
+    ("mpk_zcsr_residual", _I, [_I, _CSRP, _P, _P, _P, _P]),
     ("mpk_multicolor_order", _I, [_CSRP, _P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("mpk_csr_permute_workspace_bytes", _S, [_I64]),
     ("mpk_dcsr_permute", _I, [_CSRP, _P, _P, _P, _P, _P, _S, _P]),
@@ -193,6 +195,18 @@ def csr_spmv(A, x, y=None, trans=False, stream=None):
     _check(fn(K, ctypes.byref(A.c), int(trans), _ptr(x), _ptr(y), ctypes.c_void_p(ws_ptr), ws_n,
               _stream(stream)), "csr_spmv")
     return y
+
+
+def csr_residual(A, b, x, r=None, stream=None):
+    """r = b - A x in the vectors' precision (the solvers' true residual)."""
+    K = _vec_check(A, b, "b")
+    if _vec_check(A, x, "x") != K:
+        raise ValueError("b and x must have the same precision")
+    if r is None:
+        r = torch.empty_like(b)
+    fn = _lib().mpk_zcsr_residual if A.is_complex else _lib().mpk_dcsr_residual
+    _check(fn(K, ctypes.byref(A.c), _ptr(b), _ptr(x), _ptr(r), _stream(stream)), "csr_residual")
+    return r
 
 
 def spmv_set_lanes(A, lanes):

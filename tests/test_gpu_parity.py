@@ -78,6 +78,25 @@ def test_spmv_bitwise(mpk, orc, name, K):
 
 
 @pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv3d", "rdd"])
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_residual_bitwise(mpk, orc, name, K):
+    """r = b - A x: the oracle's SpMV, then one K-limb subtraction per
+    component (exact negation, then the oracle's addition)."""
+    p = case(name)
+    A = mpk.Csr.from_problem(p)
+    rng = np.random.default_rng(3 * K)
+    x = rand_vec(rng, p.n, p.C, K)
+    b = rand_vec(rng, p.n, p.C, K)
+    r = host(mpk.csr_residual(A, dev(b), dev(x)))
+    y = orc.spmv(p.row_ptr, p.col_idx, p.val, x)
+    ro = np.empty_like(b)
+    for i in range(p.n):
+        for c in range(p.C):
+            ro[i, c] = orc.add(b[i, c], -y[i, c])
+    assert np.array_equal(r, ro)
+
+
+@pytest.mark.parametrize("name", ["rand_real", "rand_cplx", "conv3d", "rdd"])
 @pytest.mark.parametrize("K", [1, 2, 4])
 @pytest.mark.parametrize("lanes", [2, 4, 8, 16])
 def test_spmv_vector_csr_bitwise(mpk, orc, name, K, lanes):

@@ -273,6 +273,57 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
   return true;
 }
 
+void grid_levels(const GridDims &g, std::vector<int32_t> &levptr, std::vector<int32_t> &order) {
+  const int64_t nx = g.nx, ny = g.ny, nz = g.nz, n = nx * ny * nz;
+  const int32_t nlev = int32_t(nx + ny + nz - 2);
+  // rows per level from the lines: line (y, z) holds levels y+z .. y+z+nx-1
+  auto count = [&](int64_t z0, int64_t z1, std::vector<int64_t> &cnt) {
+    std::vector<int64_t> diff(size_t(nlev) + 1, 0);
+    for (int64_t z = z0; z < z1; ++z)
+      for (int64_t y = 0; y < ny; ++y) {
+        diff[size_t(y + z)] += 1;
+        diff[size_t(y + z + nx)] -= 1;
+      }
+    cnt.assign(size_t(nlev), 0);
+    int64_t run = 0;
+    for (int32_t l = 0; l < nlev; ++l) cnt[l] = (run += diff[l]);
+  };
+  // z-slabs on up to 8 host threads: each fills its rows, level by level, at
+  // the offsets left by the slabs before it (ascending row within a level)
+  const int T = int(std::min<int64_t>(8, std::max<int64_t>(1, nz)));
+  std::vector<std::vector<int64_t>> cnt(static_cast<size_t>(T));
+  auto zb = [&](int t) { return nz * t / T; };
+  {
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back([&, t] { count(zb(t), zb(t + 1), cnt[t]); });
+    count(zb(0), zb(1), cnt[0]);
+    for (auto &x : th) x.join();
+  }
+  levptr.assign(size_t(nlev) + 1, 0);
+  for (int32_t l = 0; l < nlev; ++l) {
+    int64_t s = 0;
+    for (int t = 0; t < T; ++t) s += cnt[t][l];
+    levptr[l + 1] = levptr[l] + int32_t(s);
+  }
+  order.resize(size_t(n));
+  auto fill = [&](int t) {
+    std::vector<int64_t> next(static_cast<size_t>(nlev));
+    for (int32_t l = 0; l < nlev; ++l) {
+      int64_t o = levptr[l];
+      for (int u = 0; u < t; ++u) o += cnt[u][l];
+      next[l] = o;
+    }
+    for (int64_t z = zb(t); z < zb(t + 1); ++z)
+      for (int64_t y = 0; y < ny; ++y)
+        for (int64_t x = 0; x < nx; ++x) order[size_t(next[size_t(x + y + z)]++)] =
+            int32_t((z * ny + y) * nx + x);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(fill, t);
+  fill(0);
+  for (auto &x : th) x.join();
+}
+
 void build_plan_grid(int64_t n, int kind, HostPlan &p) {
   GridDims &g = p.grid;
   const int by = g.nz > 1 ? 8 : 64, bz = 64 / by;

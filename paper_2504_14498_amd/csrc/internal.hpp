@@ -289,6 +289,10 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz);
 // Grid sweep plan of the L (kind 0) or U (kind 1) sweep: block counts and
 // the rows that later blocks read (p.mode = 3 and the grid set before).
 void build_plan_grid(int64_t n, int kind, HostPlan &p);
+// The forward levels of a grid (row (x, y, z) is on level x + y + z) and
+// the rows in level order, ascending within a level: the factorisation's
+// order, without a pass over the pattern.
+void grid_levels(const GridDims &g, std::vector<int32_t> &levptr, std::vector<int32_t> &order);
 void build_plan_levels(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,
                        HostPlan &p);
 void build_plan_blocks(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows,

@@ -309,7 +309,10 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
         t4.join();
       });
     }
-    build_plan_levels(h, nullptr, 0, br, hp[0]);
+    if (grid)
+      grid_levels(hp[0].grid, hp[0].glob_levptr, hp[0].glob_order);
+    else
+      build_plan_levels(h, nullptr, 0, br, hp[0]);
     M->h_fac_levptr = hp[0].glob_levptr;
     int32_t init[3] = {0, INT_MAX, INT_MAX};
     if (hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,

@@ -177,6 +177,20 @@ void check_grid(const HostCsr &h, int nx, int ny, int nz, bool expect) {
   EXPECT(got == expect);
   if (!got) return;
   EXPECT(gx == nx && gy == ny && gz == nz);
+  {
+    // closed-form levels of the grid = the levels found from the pattern
+    HostPlan ref;
+    ref.mode = plan_mode(h, nullptr, 0, 0);
+    build_plan_levels(h, nullptr, 0, 0, ref);
+    GridDims gd;
+    gd.nx = gx;
+    gd.ny = gy;
+    gd.nz = gz;
+    std::vector<int32_t> levptr, order;
+    grid_levels(gd, levptr, order);
+    EXPECT(levptr == ref.glob_levptr);
+    EXPECT(order == ref.glob_order);
+  }
   for (int kind = 0; kind < 2; ++kind) {
     HostPlan hp;
     hp.mode = 3;

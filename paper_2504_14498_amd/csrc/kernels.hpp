@@ -1413,6 +1413,235 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
   }
 }
 
+// ---- grid factorisation -----------------------------------------------
+// ILU(0) (Algorithm 1) of a matrix on a 7-point or 5-point grid pattern,
+// in one launch with the forward grid sweep's walk (blocks of lines, one
+// wavefront, lane q = zl + BZ yl at x = l - yl - zl).  On this pattern no
+// update of row i reaches an entry other than its diagonal: for each lower
+// neighbour k of row i (z - 1, y - 1, x - 1: ascending column), l_ik =
+// a_ik / u_kk, then u_ii -= u_ki l_ik, where u_ki is the (unchanged) entry
+// (k, i) of row k, the only entry of row k right of the diagonal that row
+// i stores.  These are the operations, in the order, of the row-by-row
+// factorisation (ilu0_level), so the factor is the same bit for bit.  u_kk
+// comes from the lane's previous level (x - 1), lanes q - 1 and q - BZ
+// (z - 1, y - 1), or, across blocks, from `ex` (the pivots of the rows the
+// next block reads, pre-filled with the sentinel) with the bounded
+// sentinel-checked wait.
+//
+// Records (in the sweep's processing order, see grid_gather): ra[pos] holds
+// the row's three lower entries a_ik in term order and a_ii, each promoted
+// to KF limbs; rb[pos] the three entries u_ki.  The kernel overwrites ra
+// with l_ik and u_ii; grid_fac_scatter then writes them into the factor.
+static __global__ void grid_fac_gather(int64_t n, GridDims g, int by_, int C, int KF,
+                                       const int32_t *__restrict__ diag,
+                                       const double *__restrict__ val, double *__restrict__ ra,
+                                       double *__restrict__ rb) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int bz_ = WAVE / by_, V = C * KF;
+  const int64_t pl = int64_t(g.nx) * g.ny;
+  const int64_t x = i % g.nx, y = (i / g.nx) % g.ny, z = i / pl;
+  const int32_t by = int32_t(y / by_), bz = int32_t(z / bz_);
+  const int yl = int(y % by_), zl = int(z % bz_), q = zl + bz_ * yl;
+  const int64_t l = x + yl + zl;
+  int64_t pos = grid_block_start(g, by_, bz_, by, bz);
+  for (int q2 = 0; q2 < WAVE; ++q2) {
+    const int yl2 = q2 / bz_, zl2 = q2 % bz_;
+    if (int64_t(by) * by_ + yl2 >= g.ny || int64_t(bz) * bz_ + zl2 >= g.nz) continue;
+    const int64_t c = yl2 + zl2;
+    pos += min(max(l - c, int64_t(0)), int64_t(g.nx));
+    if (q2 < q && l - c >= 0 && l - c < g.nx) ++pos;
+  }
+  const bool ex = x > 0, ey = y > 0, ez = z > 0;
+  const bool xu = x < g.nx - 1, yu = y < g.ny - 1;
+  const int64_t dg = diag[i];
+  const int nlow = int(ex) + int(ey) + int(ez);
+  // term order z, y, x: lower entries of row i, and entries (k, i) of rows k
+  const bool has[3] = {ez, ey, ex};
+  const int64_t pa[3] = {dg - nlow, dg - nlow + int(ez), dg - 1};
+  const int64_t pb[3] = {ez ? diag[i - pl] + 1 + int(xu) + int(yu) : 0,
+                         ey ? diag[i - g.nx] + 1 + int(xu) : 0, ex ? diag[i - 1] + 1 : 0};
+  double *oa = ra + pos * 4 * V, *ob = rb + pos * 4 * V;
+  for (int d = 0; d < 4; ++d)
+    for (int c = 0; c < C; ++c)
+      for (int k = 0; k < KF; ++k) {
+        const double va = d == 3 ? val[dg * C + c] : (has[d] ? val[pa[d] * C + c] : 0.0);
+        const double vb = d < 3 && has[d] ? val[pb[d] * C + c] : 0.0;
+        oa[d * V + c * KF + k] = k == 0 ? va : 0.0;
+        ob[d * V + c * KF + k] = k == 0 ? vb : 0.0;
+      }
+}
+
+template <int C, int KF, int BY>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) void ilu0_grid(
+    int64_t n, GridDims g, double *ra, const double *__restrict__ rb, double *ex,
+    int32_t *ticket, int32_t *abort_flag, int32_t *bad) {
+  constexpr int BZ = grid_bz<BY>();
+  constexpr int V = C * KF;
+  __shared__ int32_t cur;
+  const int q = int(threadIdx.x);
+  const int zl = q % BZ, yl = q / BZ;
+  const int64_t plane = int64_t(g.nx) * g.ny;
+  const __amdgpu_buffer_rsrc_t Ra = buf_rsrc(ra, n * 4 * V * 8);
+  const __amdgpu_buffer_rsrc_t Rb = buf_rsrc(rb, n * 4 * V * 8);
+  const __amdgpu_buffer_rsrc_t Rx = buf_rsrc(ex, n * V * 8);
+  for (;;) {
+    if (q == 0) cur = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int32_t b = cur;
+    __syncthreads();
+    if (b >= g.nby * g.nbz) break;
+    const int32_t by = b % g.nby, bz = b / g.nby;
+    const int32_t y = by * BY + yl, z = bz * BZ + zl;
+    const bool line = y < g.ny && z < g.nz;
+    const int64_t base = int64_t(z) * plane + int64_t(y) * g.nx;
+    const bool ey = y > 0, ez = z > 0;
+    const bool exty = ey && yl == 0, extz = ez && zl == 0;
+    const bool pub = line && ((yl == BY - 1 && y < g.ny - 1) || (zl == BZ - 1 && z < g.nz - 1));
+    const int32_t nlev = g.nx + (BY - 1) + (BZ - 1);
+    int64_t run = grid_block_start(g, BY, BZ, by, bz);
+    el<C, KF> prev = el_zero<C, KF>();
+    for (int32_t l = 0; l < nlev; ++l) {
+      const int32_t x = l - yl - zl;
+      const bool a = line && x >= 0 && x < g.nx;
+      const uint64_t m = __ballot(a);
+      const int64_t pos = run + int64_t(__builtin_amdgcn_mbcnt_hi(
+                                    uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0)));
+      run += __popcll(m);
+      const uint32_t orec = a ? uint32_t(pos) * uint32_t(4 * V * 8) : BUF_OOB;
+      double fa[4 * V], fb[3 * V];
+      buf_ld_n<4 * V, 0>(Ra, orec, fa);
+      buf_ld_n<3 * V, 0>(Rb, orec, fb);
+      // pivots of the lower neighbours
+      el<C, KF> vy, vz = el_zero<C, KF>();
+      if constexpr (BZ == 1) {
+        vy = lane_prev<C, KF>(prev);
+      } else {
+        vz = lane_prev<C, KF>(prev);
+        vy = lane_read<C, KF>(prev, q >= BZ ? q - BZ : 0);
+      }
+      const int64_t is = base + x;
+      const uint32_t oy = (a && exty) ? uint32_t(is - g.nx) * uint32_t(V * 8) : BUF_OOB;
+      const uint32_t oz = (a && extz) ? uint32_t(is - plane) * uint32_t(V * 8) : BUF_OOB;
+      el<C, KF> wy, wz;
+      el_ld_agent<C, KF>(Rx, oy, wy);
+      el_ld_agent<C, KF>(Rx, oz, wz);
+      for (int it = 0;; ++it) {
+        const bool my = a && exty && el_has_sentinel<C, KF>(wy);
+        const bool mz = a && extz && el_has_sentinel<C, KF>(wz);
+        if (!(my | mz)) break;
+        if ((it & 63) == 63 && ld_agent_i(abort_flag)) break;
+        if (it >= SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        el<C, KF> ny_, nz_;
+        el_ld_agent<C, KF>(Rx, my ? oy : BUF_OOB, ny_);
+        el_ld_agent<C, KF>(Rx, mz ? oz : BUF_OOB, nz_);
+        wy = el_select<C, KF>(my, ny_, wy);
+        wz = el_select<C, KF>(mz, nz_, wz);
+      }
+      el<C, KF> u;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < KF; ++k) u.c[c].v[k] = fa[3 * V + c * KF + k];
+      double lo[3][V];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        // term order z, y, x
+        bool has;
+        el<C, KF> ukk;
+        if (d == 0) {
+          has = ez;
+          ukk = el_select<C, KF>(extz, wz, vz);
+        } else if (d == 1) {
+          has = ey;
+          ukk = el_select<C, KF>(exty, wy, vy);
+        } else {
+          has = x > 0;
+          ukk = prev;
+        }
+        double dk[V];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < KF; ++k) dk[c * KF + k] = ukk.c[c].v[k];
+        el<C, KF> aik;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < KF; ++k) aik.c[c].v[k] = fa[d * V + c * KF + k];
+        const el<C, KF> lik = el_div_k<C, KF, KF>(aik, dk);
+        const el<C, KF> un = el_sub<C, KF>(u, el_mul_f<C, KF, KF>(fb + d * V, lik));
+        u = el_select<C, KF>(has, un, u);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < KF; ++k) lo[d][c * KF + k] = has ? lik.c[c].v[k] : 0.0;
+      }
+      // results into the record (l_ik, then u_ii); the pivot of a row that
+      // the next block reads also to ex, at agent scope
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, lo[d][v]), Ra,
+                                                int(orec + uint32_t((d * V + v) * 8)), 0, 0);
+      const uint32_t ox = (a && pub) ? uint32_t(is) * uint32_t(V * 8) : BUF_OOB;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+          double v = u.c[c].v[k];
+          v = v != v ? __builtin_nan("") : v;
+          u.c[c].v[k] = v;
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Ra,
+                                                int(orec + uint32_t((3 * V + c * KF + k) * 8)), 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Rx,
+                                                int(ox + uint32_t((c * KF + k) * 8)), 0, BUF_AGENT);
+        }
+      if (a && el_is_zero<C, KF>(u)) atomicMin(bad, int32_t(is));
+      prev = el_select<C, KF>(a, u, prev);
+    }
+    __syncthreads();
+  }
+}
+
+// The factor from the records of ilu0_grid: row i's lower entries (term
+// order z, y, x, the stored ones) and its diagonal, C * KF doubles each.
+static __global__ void grid_fac_scatter(int64_t n, GridDims g, int by_, int V,
+                                        const int32_t *__restrict__ diag,
+                                        const double *__restrict__ ra, double *__restrict__ f) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int bz_ = WAVE / by_;
+  const int64_t pl = int64_t(g.nx) * g.ny;
+  const int64_t x = i % g.nx, y = (i / g.nx) % g.ny, z = i / pl;
+  const int32_t by = int32_t(y / by_), bz = int32_t(z / bz_);
+  const int yl = int(y % by_), zl = int(z % bz_), q = zl + bz_ * yl;
+  const int64_t l = x + yl + zl;
+  int64_t pos = grid_block_start(g, by_, bz_, by, bz);
+  for (int q2 = 0; q2 < WAVE; ++q2) {
+    const int yl2 = q2 / bz_, zl2 = q2 % bz_;
+    if (int64_t(by) * by_ + yl2 >= g.ny || int64_t(bz) * bz_ + zl2 >= g.nz) continue;
+    const int64_t c = yl2 + zl2;
+    pos += min(max(l - c, int64_t(0)), int64_t(g.nx));
+    if (q2 < q && l - c >= 0 && l - c < g.nx) ++pos;
+  }
+  const bool has[3] = {z > 0, y > 0, x > 0};
+  const int64_t dg = diag[i];
+  int64_t p = dg - (int(has[0]) + int(has[1]) + int(has[2]));
+  const double *r = ra + pos * 4 * V;
+  for (int d = 0; d < 3; ++d)
+    if (has[d]) {
+      for (int v = 0; v < V; ++v) f[p * V + v] = r[d * V + v];
+      ++p;
+    }
+  for (int v = 0; v < V; ++v) f[dg * V + v] = r[3 * V + v];
+}
+
 // Prepares one apply: the words that other workgroups poll filled with
 // SENTINEL (rows list1[0..cnt1) of out1 and list2[0..cnt2) of out2, or
 // rows 0..cnt-1 when a list is null: the level schedule polls every row),

@@ -123,6 +123,37 @@ static int ilu0_levels(const Ilu0 &M, hipStream_t s) {
   return MPK_OK;
 }
 
+// ILU(0) of a recognised grid in one launch (ilu0_grid): the records from
+// A, the sentinel on the pivots the next blocks read, the factorisation,
+// then the factor written into A's pattern.  Uses the L plan (grid, lines
+// per block, the list of those rows), the two plans' record arrays and
+// tmp; words[4] is its watchdog word, words[1] the zero-pivot row.
+template <int C, int KF>
+static int ilu0_grid_run(const Ilu0 &M, const double *val, hipStream_t s) {
+  const Plan &P = M.L;
+  const int64_t n = M.n;
+  const int V = C * KF;
+  hipLaunchKernelGGL(grid_fac_gather, dim3(nblocks(n)), dim3(BLOCK), 0, s, n, P.grid, P.grid_by,
+                     C, KF, (const int32_t *)M.diag, val, M.L.ell_val, M.U.ell_val);
+  hipLaunchKernelGGL(trsv_prep, dim3(nblocks(std::max<int64_t>(P.nx * V, 1))), dim3(BLOCK), 0, s,
+                     V, (const int32_t *)P.xlist, P.nx, M.tmp, (const int32_t *)nullptr,
+                     int64_t(0), (double *)nullptr, 0, (int32_t *)nullptr, 0, (int32_t *)nullptr,
+                     M.L.sync, M.U.sync, M.words + 4, (const int32_t *)nullptr);
+  const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(P.nblk, 512)));
+  if (P.grid_by == 8)
+    hipLaunchKernelGGL((ilu0_grid<C, KF, 8>), dim3(grid), dim3(WAVE), 0, s, n, P.grid,
+                       M.L.ell_val, (const double *)M.U.ell_val, M.tmp, M.L.sync, M.words + 4,
+                       M.words + 1);
+  else
+    hipLaunchKernelGGL((ilu0_grid<C, KF, 64>), dim3(grid), dim3(WAVE), 0, s, n, P.grid,
+                       M.L.ell_val, (const double *)M.U.ell_val, M.tmp, M.L.sync, M.words + 4,
+                       M.words + 1);
+  hipLaunchKernelGGL(grid_fac_scatter, dim3(nblocks(n)), dim3(BLOCK), 0, s, n, P.grid,
+                     P.grid_by, V, (const int32_t *)M.diag, (const double *)M.L.ell_val, M.f);
+  MPK_HIP(hipGetLastError());
+  return MPK_OK;
+}
+
 // Per-position schedule arrays of a plan, built on the device from the
 // uploaded row order (count, scan, fill).
 static int device_plan_arrays(Plan &P, const Ilu0 &M, int kind, hipStream_t s) {
@@ -258,6 +289,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   HostPlan hp[4];
   HostCsr ht;
   const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
+  bool grid = false;
   {
     // the schedules of the two (four) sweeps are independent: the backward
     // (and adjoint) ones are built on other host threads.  The forward
@@ -265,12 +297,13 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     // level factorisation is launched as soon as they exist and runs on the
     // device while the blocked schedules are built on the host; the forward
     // sweep's blocked schedule needs only the schedule choice and is built
-    // on its own thread meanwhile.
-    // a 7-point or 5-point grid numbered x fastest: grid sweeps for L and U
-    // (MPK_TRSV_MODE forces the other schedules)
+    // on its own thread meanwhile.  A 7-point or 5-point grid numbered x
+    // fastest gets grid sweeps for L and U and the one-launch grid
+    // factorisation, which needs no levels (MPK_TRSV_MODE forces the other
+    // schedules and the level-by-level factorisation).
     const char *force = getenv("MPK_TRSV_MODE");
     int32_t gx = 0, gy = 0, gz = 0;
-    const bool grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
+    grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
                       A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
                       A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31) &&
                       detect_grid(h, gx, gy, gz);
@@ -281,14 +314,16 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
         hp[k].grid.ny = gy;
         hp[k].grid.nz = gz;
       }
+      // the L plan first: the grid factorisation uses its block shape and
+      // its list of the rows the next blocks read
+      build_plan_grid(h.n, 0, hp[0]);
+      M->L.n = A->n;
+      if ((st = upload_plan(hp[0], M->L, s))) return st;
     } else {
       hp[0].mode = plan_mode(h, nullptr, 0, br);
     }
     std::thread t0([&] {
-      if (grid)
-        build_plan_grid(h.n, 0, hp[0]);
-      else
-        build_plan_blocks(h, nullptr, 0, br, hp[0]);
+      if (!grid) build_plan_blocks(h, nullptr, 0, br, hp[0]);
     });
     std::thread t1([&] {
       if (grid)
@@ -309,23 +344,26 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
         t4.join();
       });
     }
-    if (grid)
-      grid_levels(hp[0].grid, hp[0].glob_levptr, hp[0].glob_order);
-    else
+    if (!grid) {
       build_plan_levels(h, nullptr, 0, br, hp[0]);
-    M->h_fac_levptr = hp[0].glob_levptr;
+      M->h_fac_levptr = hp[0].glob_levptr;
+      if (hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
+                         hipMemcpyHostToDevice, s) != hipSuccess)
+        st = MPK_EDEVICE;
+    }
     int32_t init[3] = {0, INT_MAX, INT_MAX};
-    if (hipMemcpyAsync(M->fac_order, hp[0].glob_order.data(), sizeof(int32_t) * A->n,
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (!st && hipMemcpyAsync(M->words, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess)
       st = MPK_EDEVICE;
     if (!st) {
       hipLaunchKernelGGL(promote_vals, dim3(nblocks(A->nnz)), dim3(BLOCK), 0, s, A->nnz, C, KF,
                          A->val, M->f);
       st = hipGetLastError() != hipSuccess ? MPK_EDEVICE : MPK_OK;
     }
+    // the level-by-level factorisation, or on a grid the one-launch one
     if (!st)
-      st = dispatch_ck(C, KF, [&]<int CC, int KK>() { return ilu0_levels<CC, KK>(*M, s); });
+      st = dispatch_ck(C, KF, [&]<int CC, int KK>() {
+        return grid ? ilu0_grid_run<CC, KK>(*M, A->val, s) : ilu0_levels<CC, KK>(*M, s);
+      });
     t0.join();
     t1.join();
     if (adj) t2.join();
@@ -334,7 +372,8 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   MPK_PHASE("levels, factor launch, plans (host)");
   Plan *P[4] = {&M->L, &M->U, &M->UH, &M->LH};
   for (int k = 0; k < (adj ? 4 : 2); ++k) P[k]->n = A->n;
-  if ((st = upload_plan(hp[0], M->L, s)) || (st = upload_plan(hp[1], M->U, s))) return st;
+  if ((!grid && (st = upload_plan(hp[0], M->L, s))) || (st = upload_plan(hp[1], M->U, s)))
+    return st;
   M->U.div = true;
   M->L.div = false;
   M->L.kmax = M->U.kmax = M->UH.kmax = M->LH.kmax = kmax;
@@ -358,9 +397,12 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
       if ((st = device_plan_arrays(*P[k], *M, k, s))) return st;
   }
   MPK_PHASE("upload plans (after the factorisation)");
-  int32_t badpiv = INT_MAX;
+  int32_t badpiv = INT_MAX, fac_abort = 0;
   MPK_HIP(hipMemcpyAsync(&badpiv, M->words + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (grid)
+    MPK_HIP(hipMemcpyAsync(&fac_abort, M->words + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MPK_HIP(hipStreamSynchronize(s));
+  if (fac_abort) return MPK_EWATCHDOG;
   if (badpiv != INT_MAX) {
     if (info) info->bad_row = badpiv;
     return MPK_EZERO_PIVOT;

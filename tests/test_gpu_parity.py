@@ -376,6 +376,29 @@ def test_factor_errors(mpk):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("shape", [(9, 7, 6), (40, 30)])
+@pytest.mark.parametrize("kf", [1, 2])
+def test_grid_factor_zero_pivot(mpk, orc, monkeypatch, shape, kf):
+    """Zero pivots on a grid pattern: a row whose diagonal and lower entries
+    are zero has u_ii = 0 exactly; the grid factorisation and the
+    level-by-level one (forced) report the lowest such row, as the oracle."""
+    rp, ci, val = grid_problem(shape, 7)
+    val = val.copy()
+    n = len(rp) - 1
+    for k in (n // 3, n // 2):
+        for q in range(rp[k], rp[k + 1]):
+            if ci[q] <= k:
+                val[q] = 0.0
+    st, bad, f = orc.ilu0(rp, ci, val, 1, kf)
+    assert st == -4 and bad == n // 3
+    for mode in (None, "l"):
+        if mode:
+            monkeypatch.setenv("MPK_TRSV_MODE", mode)
+        with pytest.raises(mpk.MpkError) as e:
+            mpk.ilu0_factor(mpk.Csr(rp, ci, val), kf)
+        assert e.value.status == -4 and e.value.bad_row == n // 3
+
+
 def true_relres(orc, p, x, b):
     """||b - A x|| / ||b|| from the GPU's x (any limb count), by the oracle:
     the residual components are formed exactly and rounded once, so the

@@ -644,7 +644,27 @@ __global__ __launch_bounds__(BLOCK) void trsv_level(
   const int32_t i = order[pos];
   const int32_t pb = ptr[pos], pe = ptr[pos + 1];
   el<C, K> acc = el_load<C, K>(rhs + size_t(i) * E);
-  for (int32_t q = pb; q < pe; ++q) {
+  // the first U dependencies' indices and values, then their y words, are
+  // requested together (one round trip each); the terms are still
+  // subtracted one by one in ascending column order
+  constexpr int U = E <= 2 ? 4 : 2;
+  if (pe > pb) {
+    int32_t cj[U];
+    double f[U][C * KF];
+    el<C, K> yv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t q = min(pb + u, pe - 1);
+      cj[u] = col[q];
+      load_f<C, KF, CONJ>(val + size_t(q) * C * KF, f[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) yv[u] = el_load<C, K>(out + size_t(cj[u]) * E);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (pb + u < pe) acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f[u], yv[u]));
+  }
+  for (int32_t q = pb + U; q < pe; ++q) {
     double f[C * KF];
     load_f<C, KF, CONJ>(val + size_t(q) * C * KF, f);
     acc = el_sub<C, K>(acc, el_mul_f<C, K, KF>(f, el_load<C, K>(out + size_t(col[q]) * E)));
@@ -1270,6 +1290,15 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
     const bool pub = line && ((yl == BY - 1 && y < g.ny - 1) || (zl == BZ - 1 && z < g.nz - 1));
     const int32_t nlev = g.nx + (BY - 1) + (BZ - 1);
     auto real = [&](int64_t s) { return BACK ? n - 1 - s : s; };
+    // byte offsets of this lane's row at level l (row base + x, mirrored
+    // when BACK) and of its neighbours y - 1 and z - 1, as one add each
+    constexpr int64_t EB = int64_t(E) * 8;
+    const int64_t ob0 = real(base - yl - zl) * EB;  // offset of x = 0 shifted by -(yl + zl)
+    const int64_t ostep = BACK ? -EB : EB;          // per level
+    const int64_t dy = (BACK ? int64_t(g.nx) : -int64_t(g.nx)) * EB;
+    const int64_t dz = (BACK ? plane : -plane) * EB;
+    auto row_off = [&](int32_t l) { return ob0 + int64_t(l) * ostep; };
+    const int32_t slot0 = q * stride - yl - zl;     // LDS slot of this lane's row at level 0
     auto active = [&](int32_t l) {
       const int32_t x = l - yl - zl;
       return line && x >= 0 && x < g.nx;
@@ -1290,15 +1319,15 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
       for (int d = 0; d < (BACK ? 4 : 3); ++d)
 #pragma unroll
         for (int v = 0; v < V; ++v) r.f[d][v] = fr[d * V + v];
-      const uint32_t o = a ? uint32_t(real(base + (l - yl - zl))) * uint32_t(E * 8) : BUF_OOB;
+      const uint32_t o = a ? uint32_t(row_off(l)) : BUF_OOB;
       el_ld<C, K>(Rr, o, r.rh);
     };
     // external neighbours, X levels ahead
     auto stage_ext = [&](GR &r, int32_t l) {
       const bool a = active(l);
-      const int64_t is = base + (l - yl - zl);
-      const uint32_t oy = (a && exty) ? uint32_t(real(is - g.nx)) * uint32_t(E * 8) : BUF_OOB;
-      const uint32_t oz = (a && extz) ? uint32_t(real(is - plane)) * uint32_t(E * 8) : BUF_OOB;
+      const int64_t o = row_off(l);
+      const uint32_t oy = (a && exty) ? uint32_t(o + dy) : BUF_OOB;
+      const uint32_t oz = (a && extz) ? uint32_t(o + dz) : BUF_OOB;
       el_ld_agent<C, K>(Ro, oy, r.ye[0]);
       el_ld_agent<C, K>(Ro, oz, r.ye[1]);
     };
@@ -1322,17 +1351,16 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         vy = lane_read<C, K>(prev, q >= BZ ? q - BZ : 0);
       }
       if (int(el_has_sentinel<C, K>(now.ye[0])) | int(el_has_sentinel<C, K>(now.ye[1]))) {
-        // external words not written yet: re-poll them (bounded)
-        const int64_t is = base + x;
+        // external words not written yet: re-poll them (bounded; keeping a
+        // second request in flight made the sweeps slower)
+        const int64_t o = row_off(l);
         for (int it = 0;; ++it) {
           const bool my = a && exty && el_has_sentinel<C, K>(now.ye[0]);
           const bool mz = a && extz && el_has_sentinel<C, K>(now.ye[1]);
           if (!(my | mz)) break;
-          const uint32_t oy = my ? uint32_t(real(is - g.nx)) * uint32_t(E * 8) : BUF_OOB;
-          const uint32_t oz = mz ? uint32_t(real(is - plane)) * uint32_t(E * 8) : BUF_OOB;
           el<C, K> wy, wz;
-          el_ld_agent<C, K>(Ro, oy, wy);
-          el_ld_agent<C, K>(Ro, oz, wz);
+          el_ld_agent<C, K>(Ro, my ? uint32_t(o + dy) : BUF_OOB, wy);
+          el_ld_agent<C, K>(Ro, mz ? uint32_t(o + dz) : BUF_OOB, wz);
           now.ye[0] = el_select<C, K>(my, wy, now.ye[0]);
           now.ye[1] = el_select<C, K>(mz, wz, now.ye[1]);
           if ((it & 63) == 63 && ld_agent_i(abort_flag)) break;
@@ -1364,8 +1392,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         acc = el_select<C, K>(has, t, acc);
       }
       if constexpr (BACK) acc = el_div_k<C, K, KF>(acc, now.f[3]);
-      const uint32_t o = a ? uint32_t(real(base + x)) * uint32_t(E * 8) : BUF_OOB;
-      double *slot = lds + size_t(a ? q * stride + x : spare) * E;
+      const uint32_t o = a ? uint32_t(row_off(l)) : BUF_OOB;
+      double *slot = lds + size_t(a ? slot0 + l : spare) * E;
+      double w[E];
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -1373,16 +1402,37 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
           double v = acc.c[c].v[k];
           v = v != v ? __builtin_nan("") : v;
           acc.c[c].v[k] = v;
-          const uint32_t oo = o + uint32_t((c * K + k) * 8);
-          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Ro,
-                                                int(pub ? oo : BUF_OOB), 0, BUF_AGENT);
-          if constexpr (STAGE)
-            slot[c * K + k] = v;
-          else
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, v), Ro,
-                                                  int(pub ? BUF_OOB : oo), 0, 0);
+          w[c * K + k] = v;
         }
-      prev = el_select<C, K>(a, acc, prev);
+      // the row's words: at agent scope if the next block reads it (16-byte
+      // stores when E is even), and to LDS or memory for the block's copy
+      const uint32_t op = pub ? o : BUF_OOB;
+      if constexpr (E % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < E / 2; ++j) {
+          const uint64_t u0 = __builtin_bit_cast(uint64_t, w[2 * j]);
+          const uint64_t u1 = __builtin_bit_cast(uint64_t, w[2 * j + 1]);
+          const bu4 wv = {uint32_t(u0), uint32_t(u0 >> 32), uint32_t(u1), uint32_t(u1 >> 32)};
+          __builtin_amdgcn_raw_buffer_store_b128(wv, Ro, int(op + uint32_t(j * 16)), 0, BUF_AGENT);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, w[e]), Ro,
+                                                int(op + uint32_t(e * 8)), 0, BUF_AGENT);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if constexpr (STAGE)
+          slot[e] = w[e];
+        else
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu2, w[e]), Ro,
+                                                int((pub ? BUF_OOB : o) + uint32_t(e * 8)), 0, 0);
+      }
+      // lanes without a row leave garbage here; no row reads it: a lane's
+      // own value is used only for x > 0, a neighbour lane's only when that
+      // lane had a row at the previous level
+      prev = acc;
       stage_ext(ext, l + X);
       stage_row(now, l + D);
     };

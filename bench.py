@@ -18,7 +18,8 @@ passes of the same solve and scales it to a time-to-solution.
 
 Unless --no-extras, the same run also reports: the multicolour variant on
 the same system (a different preconditioner, labelled as such), the SpMV
-on random rows with the lanes-per-row sweep, the 512-system batched solve,
+on random rows with the lanes-per-row sweep, the 512-system batched solve
+(and 16 large systems, one workgroup each against teams of workgroups),
 and the learned correction against plain ILU(0).
 """
 import argparse
@@ -214,6 +215,51 @@ def measure_batched(nsys, warmup, steps, seq_sample, note):
                          "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nbytes},
             "sequential": {"sample_systems": len(samp), "sample_s": tseq,
                            "projected_s": seq_proj, "speedup": seq_proj / med}}
+
+
+def measure_batched_few(nsys, nrows, note):
+    """Fewer systems than workgroups (nsys random systems of nrows rows each,
+    as in the batched workload): one workgroup per system against the tuned
+    schedule, which gives each system a team of workgroups on one XCD.  The
+    solutions must agree bit for bit."""
+    import concurrent.futures as cf
+    import torch
+
+    from paper_2504_14498_amd import mpk
+    from paper_2504_14498_amd import workloads as W
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:
+        probs = list(pool.map(lambda q: W.random_dd(nrows, 7_000_000 + q), range(nsys)))
+    mats, bs = [], []
+    for p in probs:
+        A = mpk.Csr.from_problem(p)
+        xt = torch.zeros((p.n, 1, 2), dtype=torch.float64, device="cuda")
+        xt[:, 0, 0] = torch.as_tensor(p.x_true, device="cuda")
+        mats.append(A)
+        bs.append(mpk.csr_spmv(A, xt))
+    del probs
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res, xs_of = {}, {}
+    ws = None
+    for name, sched in (("one_workgroup_per_system", "grid=%d,order=lpt" % cus),
+                        ("tuned", None)):
+        for rep in range(2):   # the first tuned call also autotunes
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            xs, infos, st, ws = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25,
+                                                         max_iter=10000, schedule=sched,
+                                                         workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - a
+        res[name] = {"launch_s": dt, "status": st,
+                     "iters_max": max(i["iters"] for i in infos)}
+        xs_of[name] = xs
+        note("batched, %d x %d rows, %s: %s %.3f s" % (nsys, nrows, name, st, dt))
+    same = all(torch.equal(u, v) for u, v in zip(xs_of["one_workgroup_per_system"],
+                                                 xs_of["tuned"]))
+    return {"workload": "batched_random_dd nsys=%d n=%d (7-30 entries/row, BiCGSTAB-DD, "
+                        "ILU(0)-D, 1e-25)" % (nsys, nrows),
+            **res, "speedup_tuned": res["one_workgroup_per_system"]["launch_s"] /
+            res["tuned"]["launch_s"], "bitwise_equal": same}
 
 
 def measure_spmv_rows(reps, note):
@@ -637,6 +683,8 @@ def main():
         out["spmv_random_rows"] = measure_spmv_rows(args.reps, note)
         torch.cuda.empty_cache()
         out["batched"] = measure_batched(args.nsys, 1, 1, args.seq_sample, note)
+        torch.cuda.empty_cache()
+        out["batched"]["few_large_systems"] = measure_batched_few(16, 200000, note)
         torch.cuda.empty_cache()
         if os.path.exists(PARAMS_FILE):
             params, tinfo = load_params(PARAMS_FILE)

@@ -253,18 +253,24 @@ int mpk_zkrylov_solve_precond(mpk_method m, mpk_prec vp, const mpk_ilu0 *M, doub
 /* --------------------------------------------------------- batched solve
  * nsys independent real systems A[q] x[q] = b[q] of any sizes, each solved
  * by ILU(0)-preconditioned BiCGSTAB (the only method offered batched) with
- * the semantics of mpk_dkrylov_solve, in ONE persistent kernel launch: a
- * workgroup takes the next system, checks its pattern, builds its level
- * schedules, factors it (Algorithm 1) and runs the passes with the
- * substitutions of Algorithm 2, synchronising only inside the workgroup.
- * A, b, x: host arrays of nsys entries holding device pointers.  info: host
- * array of nsys reports (may be NULL).  schedule: NULL = autotune (on the
- * first call for a batch shape a few passes of each candidate schedule are
- * timed, x untouched, and the fastest is cached), or "grid=<workgroups>,
- * order=lpt|given" (lpt: systems handed out largest first).  Schedules only
- * map systems to workgroups; results are bitwise identical for every
- * schedule.  Returns MPK_OK when every system converged, otherwise the most
- * severe per-system status.  Synchronous. */
+ * the semantics of mpk_dkrylov_solve, in ONE persistent (cooperative)
+ * kernel launch: a team of workgroups on one XCD takes the next system,
+ * checks its pattern, builds its level schedules, factors it (Algorithm 1)
+ * and runs the passes with the substitutions of Algorithm 2, synchronising
+ * only inside the team.  A, b, x: host arrays of nsys entries holding
+ * device pointers.  info: host array of nsys reports (may be NULL).
+ * schedule: NULL = autotune (on the first call for a batch shape a few
+ * passes of each candidate schedule are timed, x untouched, and the
+ * fastest is cached), or "grid=<workgroups>,order=lpt|given[,team=<rows>]"
+ * (lpt: systems considered largest first; team: rows per team member, a
+ * system of n rows gets ceil(n / rows) workgroups up to the workgroups of
+ * an XCD; absent or 0: one workgroup per system).  The grid is capped at
+ * the workgroups that fit on the device at once.  Schedules only map work
+ * to workgroups: inner products are summed over fixed row tiles, so results
+ * are bitwise identical for every schedule.  A system that a launch did not
+ * finish (a team that waited past its bound) is solved again with one
+ * workgroup, from the caller's x.  Returns MPK_OK when every system
+ * converged, otherwise the most severe per-system status.  Synchronous. */
 size_t mpk_krylov_batched_workspace_bytes(mpk_method m, mpk_prec vp, mpk_prec fp, int32_t nsys,
                                           const mpk_csr *A);
 int mpk_dkrylov_solve_batched(mpk_method m, mpk_prec vp, mpk_prec fp, double tol_rel,

@@ -66,7 +66,9 @@ def test_batched_every_system_converges_like_oracle(mpk, orc, solved):
 
 def test_batched_schedules_bitwise_identical(mpk, solved):
     probs, bs, mats, xs, infos, st, ws = solved
-    for sched in ("grid=3,order=given", "grid=64,order=lpt", "grid=1,order=lpt"):
+    for sched in ("grid=3,order=given", "grid=64,order=lpt", "grid=1,order=lpt",
+                  "grid=256,order=lpt,team=1024", "grid=16,order=given,team=700",
+                  "grid=3,order=given,team=500", "grid=512,order=lpt,team=2000"):
         xs2, infos2, st2, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
                                                        tol_rel=1e-25, max_iter=2000,
                                                        schedule=sched, workspace=ws)
@@ -74,6 +76,34 @@ def test_batched_schedules_bitwise_identical(mpk, solved):
         for a, b_, i1, i2 in zip(xs, xs2, infos, infos2):
             assert i1["iters"] == i2["iters"]
             assert np.array_equal(a.cpu().numpy(), b_.cpu().numpy()), sched
+
+
+def test_batched_teams_few_large_systems(mpk, orc):
+    """Fewer systems than workgroups: each system solved by a team of
+    workgroups on one XCD (up to 12 members here), bitwise equal to one
+    workgroup per system, and the oracle's exact residual and pass count."""
+    probs = [W.random_dd(n, 4200 + n) for n in (30011, 24007, 18013, 9001)]
+    bs = [orc.spmv(p.row_ptr, p.col_idx, p.val, p.x_true_limbs(2)) for p in probs]
+    mats = [mpk.Csr.from_problem(p) for p in probs]
+    xs1, i1, st1, ws = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
+                                                tol_rel=1e-25, max_iter=500,
+                                                schedule="grid=256,order=lpt")
+    assert st1 == "ok", i1
+    for sched in ("grid=256,order=lpt,team=2500", "grid=256,order=given,team=9000"):
+        xs2, i2, st2, _ = mpk.krylov_solve_batched(mats, [dev(b) for b in bs], fprec=1,
+                                                   tol_rel=1e-25, max_iter=500, schedule=sched,
+                                                   workspace=ws)
+        assert st2 == "ok", i2
+        for a, b_, u, v in zip(xs1, xs2, i1, i2):
+            assert u["iters"] == v["iters"]
+            assert np.array_equal(a.cpu().numpy(), b_.cpu().numpy()), sched
+    for p, b, x, info in zip(probs[2:], bs[2:], xs1[2:], i1[2:]):
+        ref = orc.krylov("bicgstab", p.row_ptr, p.col_idx, p.val, b, kf=1, tol_rel=1e-25,
+                         max_iter=500)
+        assert ref["status"] == 0
+        rel = orc.true_relres(p.row_ptr, p.col_idx, p.val, b, x.cpu().numpy())
+        assert rel <= 1e-25 * RES_MARGIN, (p.name, rel)
+        assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
 
 
 def test_batched_matches_single_system_iterations(mpk, orc):

@@ -185,9 +185,10 @@ __device__ __forceinline__ void fold_tiles(const double *part, int64_t nt, BShar
 
 // Levels of one sweep, in chunks of T * BLOCK consecutive rows in the
 // sweep's order: dependencies before the chunk are final; those inside it
-// are iterated to the fixed point from below (levels only grow, so the
-// values read in a round may be old or new), one team barrier per round,
-// until a round changes nothing.  Then rows are bucketed by level
+// are iterated to the fixed point from below until a round changes nothing
+// (a team of one in LDS, two workgroup barriers per round; a larger team in
+// memory, one team barrier per round: levels only grow, so the values read
+// in a round may be old or new).  Then rows are bucketed by level
 // (counting sort; the order inside a level is irrelevant because its rows
 // are independent).  round counts the team's rounds (the same in every
 // member).
@@ -197,6 +198,7 @@ __device__ bool blevels(const BSys &S, Team &tm, BShared<K> &sh, bool lower, int
   const int tid = threadIdx.x;
   const int64_t n = S.n, gt = tm.gt(), GS = tm.gs();
   int32_t mymax = 0;
+  __shared__ int32_t tl[BLOCK];  // a team of one iterates its chunk in LDS
   for (int64_t c = 0; c < n; c += GS) {
     const int64_t t = c + gt;
     const int64_t i = lower ? t : n - 1 - t;
@@ -209,36 +211,59 @@ __device__ bool blevels(const BSys &S, Team &tm, BShared<K> &sh, bool lower, int
         const int64_t tj = lower ? j : n - 1 - j;
         if (dep && tj < c) ext = max(ext, S.lvl[j] + 1);
       }
-      S.lvl[i] = ext;
     }
     int32_t cur = ext;
-    TSYNC();
-    for (;;) {
-      int32_t l = ext;
-      if (valid) {
-        for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
-          const int32_t j = S.ci[q];
-          const bool dep = lower ? j < i : j > i;
-          const int64_t tj = lower ? j : n - 1 - j;
-          if (dep && tj >= c) l = max(l, S.lvl[j] + 1);
+    if (tm.T == 1) {
+      tl[tid] = ext;
+      __syncthreads();
+      for (;;) {
+        int32_t l = ext;
+        if (valid) {
+          for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+            const int32_t j = S.ci[q];
+            const bool dep = lower ? j < i : j > i;
+            const int64_t tj = lower ? j : n - 1 - j;
+            if (dep && tj >= c) l = max(l, tl[tj - c] + 1);
+          }
         }
+        __syncthreads();  // every read of tl in this round is done
+        const bool ch = valid && l != tl[tid];
+        if (ch) tl[tid] = l;
+        if (!__syncthreads_or(ch)) break;
       }
-      l = max(l, cur);  // levels only grow
-      const bool ch = valid && l != cur;
-      if (ch) {
-        S.lvl[i] = l;
-        cur = l;
-      }
-      if (__syncthreads_or(ch) && tid == 0) {
-        atomicMax(&tm.ctl->chg, round + 1);
-        drain();
-      }
+      cur = tl[tid];
+      if (valid) S.lvl[i] = cur;
+      __syncthreads();
+    } else {
+      if (valid) S.lvl[i] = ext;
       TSYNC();
-      // a member already in the next round may have raised chg further; a
-      // member enters that round only after some level changed in this one
-      const bool again = ld_agent_i(&tm.ctl->chg) >= round + 1;
-      ++round;
-      if (!again) break;
+      for (;;) {
+        int32_t l = ext;
+        if (valid) {
+          for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+            const int32_t j = S.ci[q];
+            const bool dep = lower ? j < i : j > i;
+            const int64_t tj = lower ? j : n - 1 - j;
+            if (dep && tj >= c) l = max(l, S.lvl[j] + 1);
+          }
+        }
+        l = max(l, cur);  // levels only grow
+        const bool ch = valid && l != cur;
+        if (ch) {
+          S.lvl[i] = l;
+          cur = l;
+        }
+        if (__syncthreads_or(ch) && tid == 0) {
+          atomicMax(&tm.ctl->chg, round + 1);
+          drain();
+        }
+        TSYNC();
+        // a member already in the next round may have raised chg further; a
+        // member enters that round only after some level changed in this one
+        const bool again = ld_agent_i(&tm.ctl->chg) >= round + 1;
+        ++round;
+        if (!again) break;
+      }
     }
     mymax = max(mymax, cur);
   }

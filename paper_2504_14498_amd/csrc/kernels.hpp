@@ -1350,7 +1350,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         vz = lane_prev<C, K>(prev);
         vy = lane_read<C, K>(prev, q >= BZ ? q - BZ : 0);
       }
-      if (int(el_has_sentinel<C, K>(now.ye[0])) | int(el_has_sentinel<C, K>(now.ye[1]))) {
+      // one wave-uniform test (lane masks in scalar registers, no divergent
+      // branch on the common path)
+      if (__ballot(el_has_sentinel<C, K>(now.ye[0])) | __ballot(el_has_sentinel<C, K>(now.ye[1]))) {
         // external words not written yet: re-poll them (bounded; keeping a
         // second request in flight made the sweeps slower)
         const int64_t o = row_off(l);

@@ -1299,10 +1299,11 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
     const int64_t dz = (BACK ? plane : -plane) * EB;
     auto row_off = [&](int32_t l) { return ob0 + int64_t(l) * ostep; };
     const int32_t slot0 = q * stride - yl - zl;     // LDS slot of this lane's row at level 0
-    auto active = [&](int32_t l) {
-      const int32_t x = l - yl - zl;
-      return line && x >= 0 && x < g.nx;
-    };
+    // the lane has a row at level l: 0 <= l - yl - zl < nx on a line of the
+    // grid, as one unsigned compare (a lane without a line gets an origin
+    // past every level used, so l - c0 < 0 for all of them)
+    const int32_t c0 = line ? yl + zl : nlev + D;
+    auto active = [&](int32_t l) { return uint32_t(l - c0) < uint32_t(g.nx); };
     // position of the next staged level's first record
     int64_t run = grid_block_start(g, BY, BZ, by, bz);
     // row data, D levels ahead: the factor record and the right-hand side

@@ -210,6 +210,9 @@ int32_t greedy_color(const HostCsr &h, IVec &color) {
 bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
   const int64_t n = h.n;
   if (n < 4) return false;
+  // the pattern may not have been checked: every read below stays inside
+  // [0, nnz) (a row is read only when its bounds lie there)
+  if (h.rp[0] != 0 || h.rp[n] != h.nnz || h.rp[n - 1] < 0 || h.rp[n - 1] > h.rp[n]) return false;
   // strides from the last row's lower columns: 1, nx (2D) and nx ny (3D)
   std::vector<int64_t> d;
   for (int32_t p = h.rp[n - 1]; p < h.rp[n] && h.ci[p] < n - 1; ++p) d.push_back(n - 1 - h.ci[p]);
@@ -239,8 +242,8 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
   std::vector<char> ok(size_t(T), 1);
   auto work = [&](int t) {
     const int64_t i0 = n * t / T, i1 = n * (t + 1) / T;
+    int64_t x = i0 % gx, y = (i0 / gx) % gy, z = i0 / pl;  // advanced row by row below
     for (int64_t i = i0; i < i1; ++i) {
-      const int64_t x = i % gx, y = (i / gx) % gy, z = i / pl;
       int64_t want[7];
       int m = 0;
       if (z > 0) want[m++] = i - pl;
@@ -250,7 +253,7 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
       if (x < gx - 1) want[m++] = i + 1;
       if (y < gy - 1) want[m++] = i + gx;
       if (z < gz - 1) want[m++] = i + pl;
-      if (h.rp[i + 1] - h.rp[i] != m) {
+      if (h.rp[i] < 0 || h.rp[i + 1] > h.nnz || h.rp[i + 1] - h.rp[i] != m) {
         ok[t] = 0;
         return;
       }
@@ -259,6 +262,13 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
           ok[t] = 0;
           return;
         }
+      if (++x == gx) {
+        x = 0;
+        if (++y == gy) {
+          y = 0;
+          ++z;
+        }
+      }
     }
   };
   std::vector<std::thread> th;

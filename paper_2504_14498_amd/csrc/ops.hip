@@ -269,10 +269,25 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   int st = fetch_pattern(A, h, s);
   if (st) return st;
   MPK_PHASE("fetch pattern");
-  st = check_pattern(h, &bad);
-  if (st) {
-    if (info) info->bad_row = bad;
-    return st;
+  const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
+  // the blocked sweeps address their arrays with 32-bit buffer offsets
+  const int64_t big = int64_t(A->n) * std::max(ELLW * C * KF, C * kmax) * 8;
+  const int br = big < (int64_t(1) << 31) ? default_block_rows(C, kmax) : 0;
+  // A 7-point or 5-point grid numbered x fastest gets grid sweeps for L and
+  // U and the one-launch grid factorisation (MPK_TRSV_MODE forces the other
+  // schedules and the level-by-level factorisation).  Recognising it checks
+  // every row against the stencil, so its pattern needs no other check.
+  const char *force = getenv("MPK_TRSV_MODE");
+  int32_t gx = 0, gy = 0, gz = 0;
+  const bool grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
+                    A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
+                    A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31) && detect_grid(h, gx, gy, gz);
+  if (!grid) {
+    st = check_pattern(h, &bad);
+    if (st) {
+      if (info) info->bad_row = bad;
+      return st;
+    }
   }
   st = csr_check_device_values(A, C, M->words + 2, &bad, s);
   if (st) {
@@ -282,14 +297,9 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   MPK_PHASE("check pattern+values");
   hipLaunchKernelGGL(find_diag, dim3(nblocks(A->n)), dim3(BLOCK), 0, s, A->n, A->row_ptr,
                      A->col_idx, M->diag);
-  const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
-  // the blocked sweeps address their arrays with 32-bit buffer offsets
-  const int64_t big = int64_t(A->n) * std::max(ELLW * C * KF, C * kmax) * 8;
-  const int br = big < (int64_t(1) << 31) ? default_block_rows(C, kmax) : 0;
   HostPlan hp[4];
   HostCsr ht;
   const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
-  bool grid = false;
   {
     // the schedules of the two (four) sweeps are independent: the backward
     // (and adjoint) ones are built on other host threads.  The forward
@@ -297,16 +307,7 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
     // level factorisation is launched as soon as they exist and runs on the
     // device while the blocked schedules are built on the host; the forward
     // sweep's blocked schedule needs only the schedule choice and is built
-    // on its own thread meanwhile.  A 7-point or 5-point grid numbered x
-    // fastest gets grid sweeps for L and U and the one-launch grid
-    // factorisation, which needs no levels (MPK_TRSV_MODE forces the other
-    // schedules and the level-by-level factorisation).
-    const char *force = getenv("MPK_TRSV_MODE");
-    int32_t gx = 0, gy = 0, gz = 0;
-    grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
-                      A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
-                      A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31) &&
-                      detect_grid(h, gx, gy, gz);
+    // on its own thread meanwhile.  The grid factorisation needs no levels.
     if (grid) {
       for (int k = 0; k < 2; ++k) {
         hp[k].mode = 3;

@@ -288,6 +288,24 @@ int main() {
       if (p.rp[k] > 5000) --p.rp[k];
     check_grid(view(p), 0, 0, 0, false);
   }
+  {
+    // detect_grid runs before the pattern checks: malformed row pointers
+    // (negative, decreasing, past nnz, a wrong total) are rejected with
+    // every read inside the arrays (the sanitizers see any other read)
+    const Pattern base = stencil(10, 9, 8);
+    const size_t n = base.rp.size() - 1;
+    const int32_t nnz = base.rp.back();
+    for (int c = 0; c < 6; ++c) {
+      Pattern p = base;
+      if (c == 0) p.rp[n / 2] = -7;
+      if (c == 1) p.rp[n / 2] = nnz + 40;
+      if (c == 2) std::swap(p.rp[n / 3], p.rp[n / 3 + 1]);
+      if (c == 3) p.rp[n] = nnz - 1;
+      if (c == 4) p.rp[n - 1] = nnz + 3;
+      if (c == 5) p.rp[0] = 2;
+      check_grid(view(p), 0, 0, 0, false);
+    }
+  }
   run(stencil(37, 1, 1), "tridiagonal");
   run(stencil(1, 1, 1), "one row");
   run(stencil(45, 33, 1), "5-point 45x33");

@@ -207,15 +207,12 @@ int32_t greedy_color(const HostCsr &h, IVec &color) {
   return ncol;
 }
 
-bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
-  const int64_t n = h.n;
+bool grid_dims_from_last_row(int64_t n, const int32_t *cols, int64_t len, int32_t &nx,
+                             int32_t &ny, int32_t &nz) {
   if (n < 4) return false;
-  // the pattern may not have been checked: every read below stays inside
-  // [0, nnz) (a row is read only when its bounds lie there)
-  if (h.rp[0] != 0 || h.rp[n] != h.nnz || h.rp[n - 1] < 0 || h.rp[n - 1] > h.rp[n]) return false;
-  // strides from the last row's lower columns: 1, nx (2D) and nx ny (3D)
+  // strides of the last row's lower neighbours: 1, nx (2D) and nx ny (3D)
   std::vector<int64_t> d;
-  for (int32_t p = h.rp[n - 1]; p < h.rp[n] && h.ci[p] < n - 1; ++p) d.push_back(n - 1 - h.ci[p]);
+  for (int64_t k = 0; k < len && cols[k] < n - 1; ++k) d.push_back(n - 1 - cols[k]);
   std::sort(d.begin(), d.end());
   if (d.empty() || d[0] != 1) return false;
   int64_t gx, gy, gz;
@@ -235,6 +232,22 @@ bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
     return false;
   }
   if (gy < 2) return false;
+  nx = int32_t(gx);
+  ny = int32_t(gy);
+  nz = int32_t(gz);
+  return true;
+}
+
+bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz) {
+  const int64_t n = h.n;
+  if (n < 4) return false;
+  // the pattern may not have been checked: every read below stays inside
+  // [0, nnz) (a row is read only when its bounds lie there)
+  if (h.rp[0] != 0 || h.rp[n] != h.nnz || h.rp[n - 1] < 0 || h.rp[n - 1] > h.rp[n]) return false;
+  int32_t ex, ey, ez;
+  if (!grid_dims_from_last_row(n, h.ci + h.rp[n - 1], h.rp[n] - h.rp[n - 1], ex, ey, ez))
+    return false;
+  const int64_t gx = ex, gy = ey, gz = ez;
   const int64_t pl = gx * gy;
   // every row stores exactly its neighbours inside the grid (and its
   // diagonal), ascending; checked on up to 8 host threads

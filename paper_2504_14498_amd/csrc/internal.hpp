@@ -285,6 +285,11 @@ int plan_mode(const HostCsr &h, const HostCsr *ht, int kind, int blk_rows);
 // The pattern is the 7-point (3D) or 5-point (2D) stencil of an nx x ny x
 // nz grid numbered x fastest (every row stores exactly its neighbours
 // inside the grid): the L and U sweeps can be grid sweeps (mode 3).
+// The extents of a grid numbered x fastest from the stored columns of its
+// last row (lower neighbours at strides 1, nx and nx ny); false when they do
+// not describe a 2D or 3D grid.
+bool grid_dims_from_last_row(int64_t n, const int32_t *cols, int64_t len, int32_t &nx,
+                             int32_t &ny, int32_t &nz);
 bool detect_grid(const HostCsr &h, int32_t &nx, int32_t &ny, int32_t &nz);
 // Grid sweep plan of the L (kind 0) or U (kind 1) sweep: block counts and
 // the rows that later blocks read (p.mode = 3 and the grid set before).

@@ -250,6 +250,64 @@ static bool timing_on() {
     }                                                                            \
   } while (0)
 
+// Row i against the stencil of an nx x ny x nz grid numbered x fastest: it
+// stores exactly its in-grid neighbours and itself, ascending (the host's
+// detect_grid test, one thread per row); otherwise *bad is set.  A row is
+// read only when its bounds lie inside [0, nnz).
+static __global__ void grid_check(int64_t n, int32_t nx, int32_t ny, int32_t nz, int64_t nnz,
+                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                  int32_t *bad) {
+  const int64_t i = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int64_t pl = int64_t(nx) * ny;
+  const int64_t x = i % nx, y = (i / nx) % ny, z = i / pl;
+  int64_t want[7];
+  int m = 0;
+  if (z > 0) want[m++] = i - pl;
+  if (y > 0) want[m++] = i - nx;
+  if (x > 0) want[m++] = i - 1;
+  want[m++] = i;
+  if (x < nx - 1) want[m++] = i + 1;
+  if (y < ny - 1) want[m++] = i + nx;
+  if (z < nz - 1) want[m++] = i + pl;
+  const int32_t a = rp[i], e = rp[i + 1];
+  bool ok = a >= 0 && e <= nnz && e - a == m;
+  for (int k = 0; ok && k < m; ++k) ok = ci[a + k] == want[k];
+  if (!ok) atomicOr(bad, 1);
+}
+
+// A grid recognised on the device, the pattern left there: the extents
+// from the last row (a few words copied), then every row checked by
+// grid_check.  yes is false (and nothing else done) when A is no grid.
+static int device_grid(const mpk_csr *A, int32_t *word, int32_t &gx, int32_t &gy, int32_t &gz,
+                       bool &yes, hipStream_t s) {
+  yes = false;
+  const int64_t n = A->n;
+  if (n < 4) return MPK_OK;
+  int32_t r[3] = {-1, -1, -1};
+  MPK_HIP(hipMemcpyAsync(&r[0], A->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipMemcpyAsync(&r[1], A->row_ptr + n - 1, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  if (r[0] != 0 || r[2] != A->nnz || r[1] < 0 || r[1] > r[2] || r[2] - r[1] > 7) return MPK_OK;
+  int32_t last[7];
+  if (r[2] > r[1]) {
+    MPK_HIP(hipMemcpyAsync(last, A->col_idx + r[1], sizeof(int32_t) * size_t(r[2] - r[1]),
+                           hipMemcpyDeviceToHost, s));
+    MPK_HIP(hipStreamSynchronize(s));
+  }
+  if (!grid_dims_from_last_row(n, last, r[2] - r[1], gx, gy, gz)) return MPK_OK;
+  const int32_t zero = 0;
+  MPK_HIP(hipMemcpyAsync(word, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(grid_check, dim3(nblocks(n)), dim3(BLOCK), 0, s, n, gx, gy, gz, A->nnz,
+                     A->row_ptr, A->col_idx, word);
+  MPK_HIP(hipGetLastError());
+  int32_t bad = 1;
+  MPK_HIP(hipMemcpyAsync(&bad, word, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPK_HIP(hipStreamSynchronize(s));
+  yes = bad == 0;
+  return MPK_OK;
+}
+
 int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_t ws_bytes,
                      Ilu0 *M, mpk_info *info, hipStream_t s) {
   const double t0 = now_ms();
@@ -266,27 +324,38 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
   M->row_ptr = A->row_ptr;
   M->col_idx = A->col_idx;
   HostCsr h;
-  int st = fetch_pattern(A, h, s);
-  if (st) return st;
-  MPK_PHASE("fetch pattern");
+  int st = MPK_OK;
   const int kmax = (flags >> 4) & 7 ? (flags >> 4) & 7 : 4;
   // the blocked sweeps address their arrays with 32-bit buffer offsets
   const int64_t big = int64_t(A->n) * std::max(ELLW * C * KF, C * kmax) * 8;
   const int br = big < (int64_t(1) << 31) ? default_block_rows(C, kmax) : 0;
+  const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
   // A 7-point or 5-point grid numbered x fastest gets grid sweeps for L and
   // U and the one-launch grid factorisation (MPK_TRSV_MODE forces the other
   // schedules and the level-by-level factorisation).  Recognising it checks
-  // every row against the stencil, so its pattern needs no other check.
+  // every row against the stencil, so its pattern needs no other check; and
+  // without adjoint schedules nothing else needs the pattern on the host, so
+  // it is recognised on the device and not copied.
   const char *force = getenv("MPK_TRSV_MODE");
   int32_t gx = 0, gy = 0, gz = 0;
-  const bool grid = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
-                    A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
-                    A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31) && detect_grid(h, gx, gy, gz);
-  if (!grid) {
-    st = check_pattern(h, &bad);
-    if (st) {
-      if (info) info->bad_row = bad;
-      return st;
+  const bool grid_ok = br > 0 && !(force && (force[0] == 'b' || force[0] == 'l' || force[0] == 's')) &&
+                       A->nnz * int64_t(C * KF) * 8 < (int64_t(1) << 31) &&
+                       A->n * int64_t(C * kmax) * 8 < (int64_t(1) << 31);
+  bool grid = false;
+  if (grid_ok && !adj && (st = device_grid(A, M->words + 8, gx, gy, gz, grid, s))) return st;
+  if (grid) {
+    h.n = A->n;  // the pattern stays on the device
+    h.nnz = A->nnz;
+  } else {
+    if ((st = fetch_pattern(A, h, s))) return st;
+    MPK_PHASE("fetch pattern");
+    grid = grid_ok && detect_grid(h, gx, gy, gz);
+    if (!grid) {
+      st = check_pattern(h, &bad);
+      if (st) {
+        if (info) info->bad_row = bad;
+        return st;
+      }
     }
   }
   st = csr_check_device_values(A, C, M->words + 2, &bad, s);
@@ -299,7 +368,6 @@ int ilu0_factor_impl(int C, int KF, const mpk_csr *A, int flags, void *ws, size_
                      A->col_idx, M->diag);
   HostPlan hp[4];
   HostCsr ht;
-  const bool adj = (flags & MPK_ILU0_ADJOINT) != 0;
   {
     // the schedules of the two (four) sweeps are independent: the backward
     // (and adjoint) ones are built on other host threads.  The forward

@@ -399,6 +399,40 @@ def test_grid_factor_zero_pivot(mpk, orc, monkeypatch, shape, kf):
         assert e.value.status == -4 and e.value.bad_row == n // 3
 
 
+def test_grid_recognition_near_grids(mpk, orc):
+    """Without adjoint schedules a grid is recognised on the device; patterns
+    that only look like one take the other schedules: a stencil row with one
+    column moved (still sorted and in range), the last row changed, and
+    broken row pointers (reported as the host's checks report them).  The
+    apply agrees with the oracle bit for bit."""
+    shape = (9, 8, 7)
+    rp, ci, val = grid_problem(shape, 21)
+    n = len(rp) - 1
+    r = rand_vec(np.random.default_rng(5), n, 1, 2)
+    cases = []
+    moved = ci.copy()
+    k = 4 * 9 * 8 + 3 * 9 + 4          # an interior row; its x + 1 entry moves to x + 2
+    q = int(np.searchsorted(ci[rp[k]:rp[k + 1]], k + 1)) + rp[k]
+    assert ci[q] == k + 1
+    moved[q] = k + 2
+    cases.append(moved)
+    last = ci.copy()
+    last[rp[n - 1]] = ci[rp[n - 1]] + 1      # the last row's z - 1 column shifted
+    cases.append(last)
+    for cc in cases:
+        A = mpk.Csr(rp, cc, val)
+        M = mpk.ilu0_factor(A, 1)
+        st, bad, f = orc.ilu0(rp, cc, val, 1, 1)
+        assert st == 0
+        assert np.array_equal(host(mpk.ilu0_apply(M, dev(r))), orc.ilu0_apply(rp, cc, f, r))
+    for cut in (n // 2, n):
+        bad_rp = rp.copy()
+        bad_rp[cut] = -5 if cut < n else rp[n] - 1
+        with pytest.raises(mpk.MpkError) as e:
+            mpk.ilu0_factor(mpk.Csr(bad_rp, ci, val), 1)
+        assert e.value.status == -8, e.value.status
+
+
 def true_relres(orc, p, x, b):
     """||b - A x|| / ||b|| from the GPU's x (any limb count), by the oracle:
     the residual components are formed exactly and rounded once, so the

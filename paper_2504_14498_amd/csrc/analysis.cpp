@@ -356,16 +356,23 @@ void build_plan_grid(int64_t n, int kind, HostPlan &p) {
   p.nblk = g.nby * g.nbz;
   // rows that the next block in y or in z reads, in the sweep's (for U
   // mirrored) coordinates: the last line of a block in y or in z
-  p.xlist.clear();
   const int64_t pl = int64_t(g.nx) * g.ny;
+  auto pub = [&](int64_t y, int64_t z) {
+    return (y % by == by - 1 && y < g.ny - 1) || (z % bz == bz - 1 && z < g.nz - 1);
+  };
+  int64_t lines = 0;
+  for (int64_t z = 0; z < g.nz; ++z)
+    for (int64_t y = 0; y < g.ny; ++y) lines += pub(y, z);
+  p.xlist.resize(size_t(lines * g.nx));  // sized once, then filled in place
+  int32_t *o = p.xlist.data();
   for (int64_t z = 0; z < g.nz; ++z)
     for (int64_t y = 0; y < g.ny; ++y) {
-      const bool pub = (y % by == by - 1 && y < g.ny - 1) || (z % bz == bz - 1 && z < g.nz - 1);
-      if (!pub) continue;
-      for (int64_t x = 0; x < g.nx; ++x) {
-        const int64_t s = z * pl + y * g.nx + x;
-        p.xlist.push_back(int32_t(kind == 1 ? n - 1 - s : s));
-      }
+      if (!pub(y, z)) continue;
+      const int64_t s0 = z * pl + y * g.nx;
+      if (kind == 1)
+        for (int64_t x = 0; x < g.nx; ++x) *o++ = int32_t(n - 1 - (s0 + x));
+      else
+        for (int64_t x = 0; x < g.nx; ++x) *o++ = int32_t(s0 + x);
     }
 }
 

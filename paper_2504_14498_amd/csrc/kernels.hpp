@@ -1086,7 +1086,11 @@ template <int C, int K, int KF> struct GridRow {
 };
 
 template <int BY> constexpr int grid_bz() { return WAVE / BY; }
-template <int E> constexpr int grid_depth() { return E <= 2 ? 6 : 4; }
+// Levels of row data (factor records, right-hand side) requested ahead:
+// eight for elements of up to two words (128^3 DD: 0.532, 0.522, 0.508,
+// 0.509, 0.505 ms per apply for 4, 6, 8, 10, 12; the unrolled loop runs up
+// to depth - 1 levels past a block's last, so 8 gives the best solve).
+template <int E> constexpr int grid_depth() { return E <= 2 ? 8 : 4; }
 // External values are requested two levels ahead: one level leaves the
 // load's latency exposed, three or more ask before the producer has
 // stored them and cost a re-poll (128^3 DD: 0.71, 0.59, 0.61, 0.66 ms per

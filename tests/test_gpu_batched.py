@@ -136,16 +136,45 @@ def test_batched_precisions(mpk, orc, fprec, K):
         assert abs(info["iters"] - ref["iters"]) <= max(3, 0.05 * ref["iters"])
 
 
-def test_batched_per_system_errors(mpk, orc):
+def drop_diagonal(p, row):
+    """CSR arrays of p without the stored diagonal of one row."""
+    q = p.row_ptr[row] + int(np.nonzero(p.col_idx[p.row_ptr[row]:p.row_ptr[row + 1]] == row)[0][0])
+    rp = p.row_ptr.copy()
+    rp[row + 1:] -= 1
+    return rp, np.delete(p.col_idx, q), np.delete(p.val, q)
+
+
+def zero_pivot(p, row):
+    """CSR arrays of p with the diagonal and lower entries of one row zeroed
+    (then u_row,row = 0 exactly)."""
+    val = p.val.copy()
+    for q in range(p.row_ptr[row], p.row_ptr[row + 1]):
+        if p.col_idx[q] <= row:
+            val[q] = 0.0
+    return p.row_ptr, p.col_idx, val
+
+
+@pytest.mark.parametrize("sched", ["grid=2,order=given", "grid=256,order=given,team=400"])
+def test_batched_per_system_errors(mpk, orc, sched):
+    # with the second schedule the 1200-row systems get teams of three
+    # workgroups: their reports come through the team's shared words
     good = W.random_dd(1500, 3)
     b = orc.spmv(good.row_ptr, good.col_idx, good.val, good.x_true_limbs(2))
     nodiag = mpk.Csr([0, 2, 3], [0, 1, 0], [1.0, 2.0, 3.0])
     zeropiv = mpk.Csr([0, 2, 4], [0, 1, 0, 1], [1.0, 1.0, 1.0, 1.0])
-    mats = [mpk.Csr.from_problem(good), nodiag, zeropiv]
-    bs = [dev(b), dev(np.ones((2, 1, 2))), dev(np.ones((2, 1, 2)))]
+    big = W.random_dd(1200, 8)
+    nodiag_big = mpk.Csr(*drop_diagonal(big, 700))
+    zeropiv_big = mpk.Csr(*zero_pivot(big, 900))
+    mats = [mpk.Csr.from_problem(good), nodiag, zeropiv, nodiag_big, zeropiv_big]
+    bs = [dev(b), dev(np.ones((2, 1, 2))), dev(np.ones((2, 1, 2))), dev(np.ones((1200, 1, 2))),
+          dev(np.ones((1200, 1, 2)))]
     xs, infos, st, _ = mpk.krylov_solve_batched(mats, bs, fprec=1, tol_rel=1e-25, max_iter=500,
-                                                schedule="grid=2,order=given")
+                                                schedule=sched)
     assert infos[0]["status"] == "ok"
     assert infos[1]["code"] == -5 and infos[1]["bad_row"] == 1
     assert infos[2]["code"] == -4 and infos[2]["bad_row"] == 1
+    assert infos[3]["code"] == -5 and infos[3]["bad_row"] == 700
+    st_o, bad_o, _ = orc.ilu0(*zero_pivot(big, 900), 1, 1)
+    assert st_o == -4
+    assert infos[4]["code"] == -4 and infos[4]["bad_row"] == bad_o
     assert st in ("eno_diag", "ezero_pivot")
